@@ -1,0 +1,171 @@
+#!/usr/bin/env python3
+"""Benchmark of the SME time step on one MI355X.
+
+A step is one full SME time step (face fluxes, non-conservative fluctuations,
+friction, CFL reduction) over every cell of the workload.  Default workload:
+the 1024 x 1024 periodic structured grid at level 2 (7 FP64 fields, 16-Gaussian
+bathymetry, 0.5 m hump), 200 steps.  Inputs are resident in HBM before the timed
+region; the timed region is K steps queued as HIP-graph replays, bracketed by
+device synchronisation, timed with HIP events on the library's stream.
+
+Prints one JSON line with the throughput (cell-updates/s), the roofline of the
+step kernel (algorithmic bytes per launch / average launch time against the
+8 TB/s HBM peak) and the CPU oracle timed on a bounded sample of the same grid.
+"""
+import argparse
+import glob
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic bytes per cell-update of the step kernel: read every field of
+# Q^n and the bathymetry once, write every field of Q^{n+1} once.
+def bytes_per_cell(kind, level):
+    nf = level + 2 if kind == "1d" else 2 * level + 3
+    b = nf * 8 * 2 + 8
+    if kind == "tri":
+        # + 3 int32 neighbour ids, 3 x (n_x, n_y, |e|/|V|) FP64 per cell
+        b += 3 * 4 + 9 * 8
+    return b
+
+
+WORKLOADS = {
+    "struct_2d_1024_l2": dict(gen="struct_2d", args={}, kernel="k_step_2d", name="struct_2d_1024x1024_level2_periodic"),
+    "tri_4m_l3": dict(gen="tri_2d", args={}, kernel="k_step_tri", name="tri_delaunay_4M_level3_walls"),
+    "dam_break_1d": dict(gen="dam_break_1d", args={}, kernel="k_step_1d", name="dam_break_1d_1000_level1"),
+    "struct_2d_4096_l2": dict(gen="struct_2d", args=dict(n=4096), kernel="k_step_2d",
+                              name="struct_2d_4096x4096_level2_periodic"),
+}
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2601_04826_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(workload, launches_bytes):
+    """HBM traffic per launch from committed rocprofv3 counter runs, if they
+    were taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("source_hash") != source_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def cpu_baseline(problem, seconds=15.0):
+    """The oracle, as is, on a bounded number of steps of the same grid."""
+    from oracle import sme as orc
+
+    o = orc.from_problem(problem)
+    q = problem["q"]
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        q, _ = o.step(q)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= seconds or steps >= problem["steps"]:
+            break
+    return dict(value=problem["ncells"] * steps / el, unit="cell-updates/s", cores=orc.max_threads(),
+                kind="oracle", sample=f"first {steps} steps of the same {problem['ncells']}-cell grid "
+                f"({el:.1f} s, OpenMP threads={orc.max_threads()})")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="struct_2d_1024_l2", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU decomposition "
+              "is a design, not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2601_04826_amd import sme, workloads
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    wl = WORKLOADS[args.workload]
+    t0 = time.perf_counter()
+    problem = getattr(workloads, wl["gen"])(**wl["args"])
+    print(f"[bench] workload {wl['name']}: {problem['ncells']} cells, level {problem['level']} "
+          f"(generated in {time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
+
+    stream = torch.cuda.Stream()
+    solver = sme.Solver(problem, stream=stream.cuda_stream)
+    solver.set_state(problem["q"])
+    torch.cuda.synchronize()
+    solver.run(args.warmup, sync=True)
+    torch.cuda.synchronize()
+
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    ev0.record(stream)
+    solver.run(args.steps, sync=False)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ms = ev0.elapsed_time(ev1)
+    t_sim, nsteps = solver.time()
+    solver.close()
+    print(f"[bench] {args.steps} steps in {ms:.3f} ms (events), {wall * 1e3:.3f} ms wall; "
+          f"simulated t = {t_sim:.6g} s over {nsteps} steps", file=sys.stderr, flush=True)
+
+    ncells = problem["ncells"]
+    value = ncells * args.steps / (ms * 1e-3)
+    per_launch_s = ms * 1e-3 / args.steps  # one step kernel per step
+    alg_bytes = bytes_per_cell(problem["kind"], problem["level"]) * ncells
+    achieved = alg_bytes / per_launch_s / 1e9
+    traffic = load_traffic(args.workload, alg_bytes)
+    out = {
+        "metric": "SME cell-updates/s (FP64)",
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": wl["name"], "cells": ncells, "level": problem["level"],
+                   "fields": problem["q"].shape[0], "cfl": problem["params"]["cfl"]},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": wl["kernel"], "alg_bytes_per_launch": alg_bytes,
+                     "avg_launch_us": per_launch_s * 1e6},
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(problem, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,162 @@
+/*
+ * sme.h -- C ABI of the MI355X shallow-moment-equation (SME) time-step library.
+ *
+ * The library advances the hierarchy of hydrostatic shallow moment equations
+ * of arXiv 2601.04826 with an explicit, first-order, path-conservative finite
+ * volume scheme:
+ *   - PDE template  dQ/dt + div F(Q) + B(Q) : grad Q = S(Q)               (Eq. (2))
+ *   - SME flux, non-conservative matrices, friction closure       (Eq. (1), Sec. 3.4)
+ *   - hydrostatic predictor then the friction ODE (Lie splitting)  (Eqs. (3a), (3d))
+ *   - finite volumes for non-conservative systems, CFL time step  (Sec. 2.1.2, Sec. 3.1)
+ * The calls mirror the paper's solver interface (Sec. 2.1.2): sme_init is the
+ * solver's initialisation (state and auxiliary data bound to a mesh and a
+ * model level), sme_run is the solve loop, sme_eigmax evaluates the model's
+ * eigenvalue bound over the state for the adaptive time step.
+ *
+ * Numbers and layout
+ *   FP64 throughout.  State Q is structure-of-arrays, Q[f * ncells + i], in the
+ *   caller's cell order:
+ *     1D       nfields = N + 2   : (h, q_0 .. q_N),          q_k = h alpha_k
+ *     2D       nfields = 2N + 3  : (h, qx_0..qx_N, qy_0..qy_N), qx_k = h alpha_k, qy_k = h beta_k
+ *   Bathymetry b[i] is static.  Units: SI, kinematic (rho = 1).
+ *
+ * Ownership
+ *   The context owns its device buffers (state ping-pong, bathymetry, mesh
+ *   geometry, time-step slots); they are allocated in sme_init and freed in
+ *   sme_destroy.  Pointers passed in are only read during the call; host or
+ *   device memory as the on_device flag says.  All device work is queued on the
+ *   HIP stream given to sme_init; a call returns once its work is queued unless
+ *   it returns a host value (sme_eigmax, sme_run with t_out/steps_done,
+ *   sme_step with dt_used, sme_get_state into host memory), which synchronises
+ *   that stream.  One context must not be used from two threads at once.
+ *
+ * Errors
+ *   Every function returns SME_OK (0) or a negative code and never throws.
+ *   sme_last_error(ctx) gives the message of the last failure on ctx;
+ *   sme_strerror(code) a generic text.
+ */
+#ifndef SME_H
+#define SME_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SME_OK 0
+#define SME_EINVAL (-1)    /* bad level, mesh, size or pointer                 */
+#define SME_ENOMEM (-2)    /* device or host allocation failed                 */
+#define SME_EHIP (-3)      /* a HIP runtime call failed (message kept)         */
+#define SME_ENONPHYS (-4)  /* h <= 0 or a non-finite value appeared            */
+#define SME_EMESH (-5)     /* degenerate triangle or non-manifold edge         */
+
+#define SME_MESH_1D 1          /* nx uniform cells on [x0, x1]                   */
+#define SME_MESH_2D_STRUCT 2   /* nx * ny cells, index j * nx + i                */
+#define SME_MESH_2D_TRI 3      /* triangles (counter-clockwise vertex order)     */
+
+#define SME_BC_PERIODIC 0      /* Periodic boundary (Sec. 2.1.1)                 */
+#define SME_BC_EXTRAP 1        /* Extrapolation boundary (Sec. 2.1.1): copy       */
+#define SME_BC_WALL 2          /* reflective wall: normal velocity mirrored       */
+
+#define SME_MAX_LEVEL 8
+
+typedef struct sme_ctx sme_ctx;
+
+/* Model parameters (Sec. 3.1, Sec. 3.4).  g gravity; c_slip the slip
+ * coefficient C of the bed closure sigma(0) = C u(0) (kinematic, m/s); nu the
+ * kinematic viscosity of the Newtonian bulk closure (m^2/s); cfl the Courant
+ * number of the adaptive step (0.45 in the paper); quad_points the number of
+ * Gauss-Legendre points (1..8) on the straight path of the non-conservative
+ * fluctuation. */
+typedef struct {
+    double g;
+    double c_slip;
+    double nu;
+    double cfl;
+    int quad_points;
+} sme_params;
+
+/* Mesh description; all arrays are host memory, copied during sme_init.
+ *   kind SME_MESH_1D        nx cells on [x0, x1]; bc[0] left, bc[1] right.
+ *   kind SME_MESH_2D_STRUCT nx * ny cells on [x0,x1] x [y0,y1];
+ *                           bc = {west, east, south, north}; periodic must pair.
+ *   kind SME_MESH_2D_TRI    n_vert vertices vert_xy[2*v + {0,1}], n_tri
+ *                           triangles tri[3*t + {0,1,2}] (CCW); every edge
+ *                           used by one triangle only is a reflective wall. */
+typedef struct {
+    int kind;
+    int64_t nx, ny;
+    double x0, x1, y0, y1;
+    int bc[4];
+    int64_t n_vert, n_tri;
+    const double *vert_xy;
+    const int32_t *tri;
+} sme_mesh;
+
+/* Number of fields and cells a (level, mesh) pair needs, without a context. */
+int sme_layout(int level, const sme_mesh *mesh, int *nfields, int64_t *ncells);
+
+/* Create a solver for the SME of the given level (0..8) on the mesh.
+ *   b       bathymetry [ncells] in caller cell order (NULL = flat), host or
+ *           device memory (b_on_device).
+ *   stream  hipStream_t to queue all work on (NULL = the null stream).
+ * The state starts at zero depth: call sme_set_state before stepping. */
+int sme_init(sme_ctx **out, int level, const sme_mesh *mesh, const sme_params *params,
+             const double *b, int b_on_device, void *stream);
+
+/* Load / read the state Q [nfields][ncells] (caller cell order; host memory,
+ * or device memory if on_device).  sme_set_state also evaluates the eigenvalue
+ * bound of the new state for the next CFL step and clears the time and step
+ * counters. */
+int sme_set_state(sme_ctx *ctx, const double *q, int on_device);
+int sme_get_state(sme_ctx *ctx, double *q, int on_device);
+
+/* Maximum wave-speed bound lam(Q, n) over all cells and face normals of the
+ * current state, and the CFL step dt = cfl * min_i 2|V_i| / sum_f |e_f| lam(Q_i, n_f)
+ * (Sec. 3.1 adaptive step).  Synchronises the stream.  Either pointer may be NULL. */
+int sme_eigmax(sme_ctx *ctx, double *lam_max, double *dt);
+
+/* One time step.  dt > 0 uses that step; dt <= 0 uses the CFL step of the
+ * current state (computed on the device, no host round trip).  If dt_used is
+ * not NULL the stream is synchronised and the step taken is returned. */
+int sme_step(sme_ctx *ctx, double dt, double *dt_used);
+
+/* n_steps CFL steps, queued as replays of a captured HIP graph.  t_end > 0
+ * stops the simulated time at t_end (the last step is shortened, later steps
+ * are no-ops).  If t_out / steps_done are not NULL the stream is synchronised
+ * and the simulated time since sme_set_state and the number of steps that
+ * advanced the state are returned; SME_ENONPHYS is returned if a step produced
+ * h <= 0 or a non-finite value (the state is then not usable). */
+int sme_run(sme_ctx *ctx, int64_t n_steps, double t_end, double *t_out, int64_t *steps_done);
+
+/* Simulated time and step count since sme_set_state (synchronises). */
+int sme_time(sme_ctx *ctx, double *t, int64_t *steps);
+
+int sme_nfields(const sme_ctx *ctx);
+int64_t sme_ncells(const sme_ctx *ctx);
+int sme_level(const sme_ctx *ctx);
+
+/* Device pointer of the current state, in the library's internal cell order
+ * (identity for 1D and structured meshes, a bandwidth-reducing permutation for
+ * triangles); field f starts at element f * sme_field_stride(ctx) (ncells
+ * rounded up to a multiple of 256).  Valid until the next step. */
+const double *sme_state_device(const sme_ctx *ctx);
+int64_t sme_field_stride(const sme_ctx *ctx);
+
+/* Introspection, host only (no device work): the FP64 basis tensors the kernels
+ * are compiled with (Eq. (1), Sec. 3.4): M[n], A[n*n*n], B[n*n*n], K[n*n] with
+ * n = level + 1, A[(i*n + j)*n + k] = <phi_i phi_j, phi_k>,
+ * B[(i*n + j)*n + k] = <phi_i Phi_j, phi_k'>, K[j*n + k] = <phi_j', phi_k'>.
+ * Any pointer may be NULL. */
+int sme_basis_tensors(int level, double *M, double *A, double *B, double *K);
+
+const char *sme_strerror(int code);
+const char *sme_last_error(const sme_ctx *ctx);
+void sme_destroy(sme_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SME_H */

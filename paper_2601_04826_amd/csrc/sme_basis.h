@@ -1,0 +1,156 @@
+// sme_basis.h -- compile-time basis tensors of the shallow moment equations.
+//
+// The vertical velocity is expanded in the shifted Legendre family
+// phi_k(zeta) = P_k(1 - 2 zeta), zeta in [0, 1] with zeta = 0 at the bed
+// (Sec. 2.1.1, "Basismatrices"; Eq. (1)).  The model needs the depth integrals
+//   M_k   = <phi_k, phi_k>,      A_ijk = <phi_i phi_j, phi_k>,
+//   B_ijk = <phi_i Phi_j, phi_k'> with Phi_j(zeta) = int_0^zeta phi_j,
+//   K_jk  = <phi_j', phi_k'>     (Newtonian bulk friction, Sec. 3.4).
+// They are evaluated here at compile time, exactly: every phi_k has integer
+// coefficients in zeta, products stay integer (__int128), and the integral over
+// [0, 1] of sum_m c_m zeta^m is the fraction sum_m c_m / (m + 1), reduced once
+// and rounded once to double.  Being constexpr, the kernels see the tensors as
+// literals, so structurally zero entries cost nothing after unrolling.
+#pragma once
+
+#include <stdint.h>
+
+namespace sme {
+
+constexpr int kMaxLevel = 8;
+constexpr int kMaxDeg = 3 * kMaxLevel + 2;  // degree bound of any triple product below
+
+struct IPoly {               // integer polynomial in zeta, scaled by `scale`
+    __int128 c[kMaxDeg + 1];
+    int deg;
+};
+
+constexpr __int128 iabs128(__int128 a) { return a < 0 ? -a : a; }
+constexpr __int128 gcd128(__int128 a, __int128 b)
+{
+    a = iabs128(a);
+    b = iabs128(b);
+    while (b != 0) {
+        __int128 t = a % b;
+        a = b;
+        b = t;
+    }
+    return a;
+}
+
+constexpr IPoly pzero()
+{
+    IPoly p{};
+    for (int i = 0; i <= kMaxDeg; ++i) p.c[i] = 0;
+    p.deg = 0;
+    return p;
+}
+
+constexpr IPoly pmul(const IPoly &a, const IPoly &b)
+{
+    IPoly r = pzero();
+    for (int i = 0; i <= a.deg; ++i)
+        for (int j = 0; j <= b.deg; ++j) r.c[i + j] += a.c[i] * b.c[j];
+    r.deg = a.deg + b.deg;
+    return r;
+}
+
+constexpr IPoly pder(const IPoly &a)
+{
+    IPoly r = pzero();
+    for (int i = 1; i <= a.deg; ++i) r.c[i - 1] = a.c[i] * i;
+    r.deg = a.deg > 0 ? a.deg - 1 : 0;
+    return r;
+}
+
+// shifted Legendre phi_k(zeta) = P_k(1 - 2 zeta) has integer coefficients:
+// phi_k(zeta) = sum_m (-1)^m C(k, m) C(k + m, m) zeta^m.
+constexpr __int128 binom(int n, int k)
+{
+    __int128 r = 1;
+    for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+    return r;
+}
+
+constexpr IPoly phi(int k)
+{
+    IPoly r = pzero();
+    for (int m = 0; m <= k; ++m) r.c[m] = ((m % 2) ? -1 : 1) * binom(k, m) * binom(k + m, m);
+    r.deg = k;
+    return r;
+}
+
+// lcm(1..9) = 2520 makes 2520 * Phi_j an integer polynomial for every j <= 8
+constexpr __int128 kPhiScale = 2520;
+
+// kPhiScale * Phi_j(zeta), Phi_j(0) = 0
+constexpr IPoly phi_int_scaled(int j)
+{
+    IPoly p = phi(j);
+    IPoly r = pzero();
+    for (int m = 0; m <= p.deg; ++m) r.c[m + 1] = p.c[m] * (kPhiScale / (m + 1));
+    r.deg = p.deg + 1;
+    return r;
+}
+
+// exact int_0^1 p / scale, rounded once to double
+constexpr double integrate(const IPoly &p, __int128 scale)
+{
+    __int128 den = 1;  // lcm(1..deg+1)
+    for (int m = 1; m <= p.deg + 1; ++m) den = den / gcd128(den, m) * m;
+    __int128 num = 0;
+    for (int m = 0; m <= p.deg; ++m) num += p.c[m] * (den / (m + 1));
+    den *= scale;
+    __int128 g = gcd128(num, den);
+    if (g != 0) {
+        num /= g;
+        den /= g;
+    }
+    return (double)num / (double)den;
+}
+
+template <int N>
+struct Tensors {
+    static constexpr int n = N + 1;
+    double M[n];
+    double invM[n];
+    double A[n][n][n];
+    double B[n][n][n];
+    double K[n][n];
+};
+
+template <int N>
+constexpr Tensors<N> make_tensors()
+{
+    constexpr int n = N + 1;
+    Tensors<N> t{};
+    IPoly ph[n] = {}, dph[n] = {}, Ph[n] = {};
+    for (int k = 0; k < n; ++k) {
+        ph[k] = phi(k);
+        dph[k] = pder(ph[k]);
+        Ph[k] = phi_int_scaled(k);
+    }
+    for (int k = 0; k < n; ++k) {
+        t.M[k] = integrate(pmul(ph[k], ph[k]), 1);
+        t.invM[k] = (double)(2 * k + 1);  // exact: M_k = 1 / (2k + 1)
+    }
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            IPoly pij = pmul(ph[i], ph[j]);
+            IPoly qij = pmul(ph[i], Ph[j]);
+            for (int k = 0; k < n; ++k) {
+                t.A[i][j][k] = integrate(pmul(pij, ph[k]), 1);
+                t.B[i][j][k] = integrate(pmul(qij, dph[k]), kPhiScale);
+            }
+        }
+    for (int j = 0; j < n; ++j)
+        for (int k = 0; k < n; ++k) t.K[j][k] = integrate(pmul(dph[j], dph[k]), 1);
+    return t;
+}
+
+template <int N>
+struct Basis {
+    static constexpr Tensors<N> T = make_tensors<N>();
+};
+
+}  // namespace sme

@@ -1,0 +1,67 @@
+// sme_kernels.h -- launch interface between the host library and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sme_device.h"
+
+namespace sme {
+
+// Per-step bookkeeping on the device.  Three slots rotate: step n reads slot a
+// (time, CFL ratio of Q^n), writes slot b (time and CFL ratio of Q^{n+1}) and
+// clears slot c for step n + 1.  rbits holds max_i r_i (r_i = sum_f |e_f| lam /
+// (2 |V_i|)) as the bit pattern of a non-negative double, so an unsigned
+// atomic max is an exact, order-independent maximum.
+struct Slot {
+    unsigned long long rbits;   // max CFL ratio of the state this slot describes
+    unsigned long long lbits;   // max lam over cells and face normals
+    double t;                   // simulated time of that state
+    double dt;                  // step that produced it
+    long long step;             // number of steps that advanced the state
+    long long pad[3];
+};
+
+struct ErrWord {
+    unsigned int flag;          // 1 once a non-physical value was produced
+    unsigned int pad;
+    unsigned long long first_step;  // smallest step index that produced one
+};
+
+enum BcKind { BC_PERIODIC = 0, BC_EXTRAP = 1, BC_WALL = 2 };
+
+struct StepArgs {
+    const double *q;     // Q^n, SoA with `stride`
+    double *qn;          // Q^{n+1}
+    const double *b;
+    int64_t stride;
+    int64_t ncells;
+    // structured / 1D
+    int nx, ny;
+    double idx, idy;     // 1/dx, 1/dy
+    int bc[4];           // W, E, S, N
+    int rows;            // rows per wave strip (structured 2D)
+    // triangles (internal order)
+    const int32_t *nbr;  // [3][stride]
+    const double *fnx, *fny, *fw;  // [3][stride], fw = |e| / |V|
+    // model
+    double g, c_slip, nu, cfl;
+    Quad quad;
+    // time stepping
+    double dt_fixed;     // > 0: fixed step
+    double t_end;        // > 0: clamp simulated time
+    Slot *slots;
+    int sa, sb, sc;
+    ErrWord *err;
+};
+
+// host-side launchers (defined in sme_kernels.hip); level is 0..8
+hipError_t launch_step_1d(int level, const StepArgs &a, hipStream_t s);
+hipError_t launch_step_2d(int level, const StepArgs &a, hipStream_t s);
+hipError_t launch_step_tri(int level, const StepArgs &a, hipStream_t s);
+hipError_t launch_eig(int dim, int kind, int level, const StepArgs &a, hipStream_t s);
+hipError_t launch_slots_reset(Slot *slots, ErrWord *err, int sa, hipStream_t s);
+hipError_t launch_permute(const double *src, int64_t sstride, double *dst, int64_t dstride,
+                          const int64_t *map, int64_t ncells, int nf, hipStream_t s);
+
+}  // namespace sme

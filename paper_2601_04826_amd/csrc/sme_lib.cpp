@@ -1,0 +1,716 @@
+// sme_lib.cpp -- host side of the SME library: the C ABI declared in include/sme.h.
+//
+// Owns the per-context device memory, prepares mesh geometry (triangle
+// neighbours, normals, a reverse Cuthill-McKee cell order), the Gauss-Legendre
+// points of the path integral, and queues the step kernels, capturing runs of
+// steps in HIP graphs so a long run costs one graph launch per six steps.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/sme.h"
+#include "sme_kernels.h"
+
+using namespace sme;
+
+namespace {
+
+constexpr int kGraphSteps = 6;  // lcm of the ping-pong period (2) and the slot period (3)
+
+struct GraphEntry {
+    int cur, slot;
+    double t_end;
+    hipGraphExec_t exec;
+};
+
+}  // namespace
+
+struct sme_ctx {
+    int level = 0;
+    int kind = 0;
+    int nf = 0;
+    int64_t ncells = 0;
+    int64_t stride = 0;
+    int64_t nx = 0, ny = 0;
+    double dx = 0, dy = 0;
+    int bc[4] = {0, 0, 0, 0};
+    int rows = 16;
+    sme_params p{};
+    Quad quad{};
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int device = 0;
+    // device memory
+    double *q[2] = {nullptr, nullptr};
+    double *b = nullptr;
+    int32_t *nbr = nullptr;
+    double *fnx = nullptr, *fny = nullptr, *fw = nullptr;
+    int64_t *to_internal = nullptr;  // caller cell -> internal cell (triangles)
+    int64_t *to_caller = nullptr;    // internal cell -> caller cell
+    Slot *slots = nullptr;
+    ErrWord *err = nullptr;
+    int cur = 0;   // which q[] holds the state
+    int sa = 0;    // slot describing the current state
+    bool has_state = false;
+    std::vector<GraphEntry> graphs;
+    std::string last;
+};
+
+namespace {
+
+int fail(sme_ctx *c, int code, const char *fmt, ...)
+{
+    if (c) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        c->last = buf;
+    }
+    return code;
+}
+
+#define HIPCHK(ctx, call)                                                                          \
+    do {                                                                                           \
+        hipError_t e_ = (call);                                                                    \
+        if (e_ != hipSuccess)                                                                      \
+            return fail((ctx), SME_EHIP, "%s failed: %s", #call, hipGetErrorString(e_));          \
+    } while (0)
+
+int nfields_of(int level, int kind) { return kind == SME_MESH_1D ? level + 2 : 2 * level + 3; }
+
+// Gauss-Legendre points on [0, 1] (weights sum to 1) by Newton's method on P_n.
+void gauss_legendre01(int n, double *s, double *w)
+{
+    for (int i = 0; i < n; ++i) {
+        long double x = cosl(3.14159265358979323846264338327950288L * (i + 0.75L) / (n + 0.5L));
+        long double dp = 0;
+        for (int it = 0; it < 100; ++it) {
+            long double p0 = 1, p1 = x;
+            for (int k = 2; k <= n; ++k) {
+                long double p2 = ((2 * k - 1) * x * p1 - (k - 1) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            if (n == 1) {
+                p1 = x;
+                p0 = 1;
+            }
+            dp = n * (x * p1 - p0) / (x * x - 1);
+            long double dx = p1 / dp;
+            x -= dx;
+            if (fabsl(dx) < 1e-30L) break;
+        }
+        long double p0 = 1, p1 = x;
+        for (int k = 2; k <= n; ++k) {
+            long double p2 = ((2 * k - 1) * x * p1 - (k - 1) * p0) / k;
+            p0 = p1;
+            p1 = p2;
+        }
+        if (n == 1) {
+            p1 = x;
+            p0 = 1;
+        }
+        dp = n * (x * p1 - p0) / (x * x - 1);
+        long double wi = 2.0L / ((1 - x * x) * dp * dp);
+        s[i] = (double)(0.5L * (1.0L - x));
+        w[i] = (double)(0.5L * wi);
+    }
+}
+
+int check_mesh(const sme_mesh *m, int level, int *nf, int64_t *nc)
+{
+    if (!m || level < 0 || level > SME_MAX_LEVEL) return SME_EINVAL;
+    *nf = nfields_of(level, m->kind);
+    switch (m->kind) {
+    case SME_MESH_1D:
+        if (m->nx < 1 || m->nx > (int64_t)1 << 30 || !(m->x1 > m->x0)) return SME_EINVAL;
+        for (int s = 0; s < 2; ++s)
+            if (m->bc[s] < 0 || m->bc[s] > 2) return SME_EINVAL;
+        if ((m->bc[0] == SME_BC_PERIODIC) != (m->bc[1] == SME_BC_PERIODIC)) return SME_EINVAL;
+        *nc = m->nx;
+        return SME_OK;
+    case SME_MESH_2D_STRUCT:
+        if (m->nx < 1 || m->ny < 1 || m->nx > (int64_t)1 << 24 || m->ny > (int64_t)1 << 24) return SME_EINVAL;
+        if (m->nx * m->ny > ((int64_t)1 << 31) - 1) return SME_EINVAL;
+        if (!(m->x1 > m->x0) || !(m->y1 > m->y0)) return SME_EINVAL;
+        for (int s = 0; s < 4; ++s)
+            if (m->bc[s] < 0 || m->bc[s] > 2) return SME_EINVAL;
+        if ((m->bc[0] == SME_BC_PERIODIC) != (m->bc[1] == SME_BC_PERIODIC)) return SME_EINVAL;
+        if ((m->bc[2] == SME_BC_PERIODIC) != (m->bc[3] == SME_BC_PERIODIC)) return SME_EINVAL;
+        *nc = m->nx * m->ny;
+        return SME_OK;
+    case SME_MESH_2D_TRI:
+        if (m->n_tri < 1 || m->n_vert < 3 || !m->vert_xy || !m->tri) return SME_EINVAL;
+        if (m->n_tri > ((int64_t)1 << 31) - 1) return SME_EINVAL;
+        *nc = m->n_tri;
+        return SME_OK;
+    default:
+        return SME_EINVAL;
+    }
+}
+
+// Triangle geometry in caller order: neighbour (or -1 = wall), outward unit
+// normal, |e| / |V| for face s = edge (v_s, v_{s+1}).
+struct TriGeom {
+    std::vector<int32_t> nbr;
+    std::vector<double> nx, ny, w;
+};
+
+int build_tri(sme_ctx *c, const sme_mesh *m, TriGeom &g)
+{
+    const int64_t nt = m->n_tri, nv = m->n_vert;
+    g.nbr.assign(3 * nt, -1);
+    g.nx.resize(3 * nt);
+    g.ny.resize(3 * nt);
+    g.w.resize(3 * nt);
+    const double *X = m->vert_xy;
+    const int32_t *T = m->tri;
+    for (int64_t t = 0; t < nt; ++t) {
+        int32_t v[3] = {T[3 * t], T[3 * t + 1], T[3 * t + 2]};
+        for (int s = 0; s < 3; ++s)
+            if (v[s] < 0 || v[s] >= nv) return fail(c, SME_EMESH, "triangle %lld has a bad vertex index", (long long)t);
+        double ax = X[2 * v[0]], ay = X[2 * v[0] + 1];
+        double bx = X[2 * v[1]], by = X[2 * v[1] + 1];
+        double cx = X[2 * v[2]], cy = X[2 * v[2] + 1];
+        double area = 0.5 * ((bx - ax) * (cy - ay) - (cx - ax) * (by - ay));
+        if (!(area > 0.0))
+            return fail(c, SME_EMESH, "triangle %lld is degenerate or not counter-clockwise", (long long)t);
+        for (int s = 0; s < 3; ++s) {
+            int32_t p0 = v[s], p1 = v[(s + 1) % 3];
+            double ex = X[2 * p1] - X[2 * p0];
+            double ey = X[2 * p1 + 1] - X[2 * p0 + 1];
+            double len = std::sqrt(ex * ex + ey * ey);
+            g.nx[3 * t + s] = ey / len;
+            g.ny[3 * t + s] = -ex / len;
+            g.w[3 * t + s] = len / area;
+        }
+    }
+    // match half-edges: key (min, max) vertex pair
+    struct HE {
+        uint64_t key;
+        int64_t id;  // 3 * t + s
+    };
+    std::vector<HE> he(3 * nt);
+    for (int64_t t = 0; t < nt; ++t)
+        for (int s = 0; s < 3; ++s) {
+            uint64_t a = (uint32_t)T[3 * t + s], b = (uint32_t)T[3 * t + (s + 1) % 3];
+            uint64_t lo = std::min(a, b), hi = std::max(a, b);
+            he[3 * t + s] = HE{lo * (uint64_t)nv + hi, 3 * t + s};
+        }
+    std::sort(he.begin(), he.end(), [](const HE &x, const HE &y) { return x.key < y.key || (x.key == y.key && x.id < y.id); });
+    for (size_t k = 0; k < he.size();) {
+        size_t e = k + 1;
+        while (e < he.size() && he[e].key == he[k].key) ++e;
+        if (e - k > 2) return fail(c, SME_EMESH, "non-manifold edge (used by %zu triangles)", e - k);
+        if (e - k == 2) {
+            int64_t i0 = he[k].id, i1 = he[k + 1].id;
+            // consistent orientation: the two triangles traverse the edge in opposite directions
+            int32_t a0 = T[i0], b0 = T[(i0 / 3) * 3 + (i0 % 3 + 1) % 3];
+            int32_t a1 = T[i1], b1 = T[(i1 / 3) * 3 + (i1 % 3 + 1) % 3];
+            if (!(a0 == b1 && b0 == a1)) return fail(c, SME_EMESH, "inconsistently oriented neighbours");
+            g.nbr[i0] = (int32_t)(i1 / 3);
+            g.nbr[i1] = (int32_t)(i0 / 3);
+        }
+        k = e;
+    }
+    return SME_OK;
+}
+
+// Reverse Cuthill-McKee order of the triangle adjacency graph.
+// Returns order[k] = caller cell placed at internal position k.
+std::vector<int64_t> rcm_order(const std::vector<int32_t> &nbr, int64_t n)
+{
+    std::vector<int> deg(n, 0);
+    for (int64_t i = 0; i < n; ++i)
+        for (int s = 0; s < 3; ++s) deg[i] += nbr[3 * i + s] >= 0;
+    std::vector<int64_t> order;
+    order.reserve(n);
+    std::vector<char> seen(n, 0);
+    std::vector<int64_t> level_of(n, -1);
+    auto bfs_last = [&](int64_t start) {
+        // plain BFS, returns a node of the last level with minimum degree
+        std::vector<int64_t> q{start};
+        std::vector<int64_t> mark;
+        level_of[start] = 0;
+        mark.push_back(start);
+        size_t h = 0;
+        while (h < q.size()) {
+            int64_t u = q[h++];
+            for (int s = 0; s < 3; ++s) {
+                int32_t v = nbr[3 * u + s];
+                if (v >= 0 && level_of[v] < 0) {
+                    level_of[v] = level_of[u] + 1;
+                    q.push_back(v);
+                    mark.push_back(v);
+                }
+            }
+        }
+        int64_t best = q.back();
+        int64_t L = level_of[best];
+        for (auto it = q.rbegin(); it != q.rend() && level_of[*it] == L; ++it)
+            if (deg[*it] < deg[best]) best = *it;
+        for (int64_t m : mark) level_of[m] = -1;
+        return best;
+    };
+    for (int64_t root = 0; root < n; ++root) {
+        if (seen[root]) continue;
+        int64_t start = bfs_last(bfs_last(root));  // pseudo-peripheral start
+        size_t h = order.size();
+        order.push_back(start);
+        seen[start] = 1;
+        while (h < order.size()) {
+            int64_t u = order[h++];
+            int64_t cand[3];
+            int nc = 0;
+            for (int s = 0; s < 3; ++s) {
+                int32_t v = nbr[3 * u + s];
+                if (v >= 0 && !seen[v]) {
+                    seen[v] = 1;
+                    cand[nc++] = v;
+                }
+            }
+            std::sort(cand, cand + nc, [&](int64_t x, int64_t y) { return deg[x] < deg[y] || (deg[x] == deg[y] && x < y); });
+            for (int k = 0; k < nc; ++k) order.push_back(cand[k]);
+        }
+    }
+    std::reverse(order.begin(), order.end());
+    return order;
+}
+
+template <typename T>
+int dalloc(sme_ctx *c, T **p, size_t count)
+{
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc((void **)p, count * sizeof(T));
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return fail(c, e == hipErrorOutOfMemory ? SME_ENOMEM : SME_EHIP, "hipMalloc(%zu bytes): %s",
+                    count * sizeof(T), hipGetErrorString(e));
+    }
+    return SME_OK;
+}
+
+StepArgs make_args(const sme_ctx *c)
+{
+    StepArgs a{};
+    a.q = c->q[c->cur];
+    a.qn = c->q[1 - c->cur];
+    a.b = c->b;
+    a.stride = c->stride;
+    a.ncells = c->ncells;
+    a.nx = (int)c->nx;
+    a.ny = (int)c->ny;
+    a.idx = c->dx > 0 ? 1.0 / c->dx : 0.0;
+    a.idy = c->dy > 0 ? 1.0 / c->dy : 0.0;
+    for (int s = 0; s < 4; ++s) a.bc[s] = c->bc[s];
+    a.rows = c->rows;
+    a.nbr = c->nbr;
+    a.fnx = c->fnx;
+    a.fny = c->fny;
+    a.fw = c->fw;
+    a.g = c->p.g;
+    a.c_slip = c->p.c_slip;
+    a.nu = c->p.nu;
+    a.cfl = c->p.cfl;
+    a.quad = c->quad;
+    a.slots = c->slots;
+    a.sa = c->sa;
+    a.sb = (c->sa + 1) % 3;
+    a.sc = (c->sa + 2) % 3;
+    a.err = c->err;
+    return a;
+}
+
+hipError_t launch_one_step(sme_ctx *c, double dt_fixed, double t_end)
+{
+    StepArgs a = make_args(c);
+    a.dt_fixed = dt_fixed;
+    a.t_end = t_end;
+    hipError_t e;
+    switch (c->kind) {
+    case SME_MESH_1D: e = launch_step_1d(c->level, a, c->stream); break;
+    case SME_MESH_2D_STRUCT: e = launch_step_2d(c->level, a, c->stream); break;
+    default: e = launch_step_tri(c->level, a, c->stream); break;
+    }
+    if (e == hipSuccess) {
+        c->cur = 1 - c->cur;
+        c->sa = (c->sa + 1) % 3;
+    }
+    return e;
+}
+
+void drop_graphs(sme_ctx *c)
+{
+    for (auto &g : c->graphs) (void)hipGraphExecDestroy(g.exec);
+    c->graphs.clear();
+}
+
+int get_graph(sme_ctx *c, double t_end, hipGraphExec_t *out)
+{
+    for (auto &g : c->graphs)
+        if (g.cur == c->cur && g.slot == c->sa && g.t_end == t_end) {
+            *out = g.exec;
+            return SME_OK;
+        }
+    const int cur0 = c->cur, sa0 = c->sa;
+    HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    hipError_t le = hipSuccess;
+    for (int k = 0; k < kGraphSteps && le == hipSuccess; ++k) le = launch_one_step(c, 0.0, t_end);
+    hipGraph_t graph = nullptr;
+    hipError_t ee = hipStreamEndCapture(c->stream, &graph);
+    c->cur = cur0;
+    c->sa = sa0;
+    if (le != hipSuccess || ee != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return fail(c, SME_EHIP, "graph capture failed: %s", hipGetErrorString(le != hipSuccess ? le : ee));
+    }
+    hipGraphExec_t exec = nullptr;
+    hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess) return fail(c, SME_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(ie));
+    c->graphs.push_back(GraphEntry{cur0, sa0, t_end, exec});
+    *out = exec;
+    return SME_OK;
+}
+
+int read_slot(sme_ctx *c, Slot *s, ErrWord *e)
+{
+    HIPCHK(c, hipMemcpyAsync(s, c->slots + c->sa, sizeof(Slot), hipMemcpyDeviceToHost, c->stream));
+    if (e) HIPCHK(c, hipMemcpyAsync(e, c->err, sizeof(ErrWord), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return SME_OK;
+}
+
+template <int N>
+void copy_tensors(double *M, double *A, double *B, double *K)
+{
+    constexpr int n = N + 1;
+    const auto &T = Basis<N>::T;
+    for (int i = 0; i < n; ++i) {
+        if (M) M[i] = T.M[i];
+        for (int j = 0; j < n; ++j) {
+            if (K) K[i * n + j] = T.K[i][j];
+            for (int k = 0; k < n; ++k) {
+                if (A) A[(i * n + j) * n + k] = T.A[i][j][k];
+                if (B) B[(i * n + j) * n + k] = T.B[i][j][k];
+            }
+        }
+    }
+}
+}  // namespace
+
+extern "C" {
+
+int sme_layout(int level, const sme_mesh *mesh, int *nfields, int64_t *ncells)
+{
+    int nf = 0;
+    int64_t nc = 0;
+    int r = check_mesh(mesh, level, &nf, &nc);
+    if (r != SME_OK) return r;
+    if (nfields) *nfields = nf;
+    if (ncells) *ncells = nc;
+    return SME_OK;
+}
+
+int sme_init(sme_ctx **out, int level, const sme_mesh *mesh, const sme_params *params, const double *b,
+             int b_on_device, void *stream)
+{
+    if (!out || !params) return SME_EINVAL;
+    *out = nullptr;
+    int nf;
+    int64_t nc;
+    int r = check_mesh(mesh, level, &nf, &nc);
+    if (r != SME_OK) return r;
+    if (params->quad_points < 1 || params->quad_points > kMaxQuad || !(params->cfl > 0) || !(params->g > 0) ||
+        params->c_slip < 0 || params->nu < 0)
+        return SME_EINVAL;
+    sme_ctx *c = new (std::nothrow) sme_ctx();
+    if (!c) return SME_ENOMEM;
+    c->level = level;
+    c->kind = mesh->kind;
+    c->nf = nf;
+    c->ncells = nc;
+    c->stride = (nc + 255) / 256 * 256;
+    c->p = *params;
+    c->quad.n = params->quad_points;
+    gauss_legendre01(params->quad_points, c->quad.s, c->quad.w);
+    for (int s = 0; s < 4; ++s) c->bc[s] = mesh->bc[s];
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return SME_EHIP;
+    }
+    if (stream) {
+        c->stream = (hipStream_t)stream;
+    } else {
+        if (hipStreamCreate(&c->stream) != hipSuccess) {
+            delete c;
+            return SME_EHIP;
+        }
+        c->own_stream = true;
+    }
+    if (mesh->kind == SME_MESH_1D) {
+        c->nx = mesh->nx;
+        c->ny = 1;
+        c->dx = (mesh->x1 - mesh->x0) / mesh->nx;
+    } else if (mesh->kind == SME_MESH_2D_STRUCT) {
+        c->nx = mesh->nx;
+        c->ny = mesh->ny;
+        c->dx = (mesh->x1 - mesh->x0) / mesh->nx;
+        c->dy = (mesh->y1 - mesh->y0) / mesh->ny;
+        const char *env = getenv("SME_ROWS");
+        c->rows = env ? std::max(1, atoi(env)) : 16;
+    }
+    int rc = SME_OK;
+    rc = rc ? rc : dalloc(c, &c->q[0], (size_t)nf * c->stride);
+    rc = rc ? rc : dalloc(c, &c->q[1], (size_t)nf * c->stride);
+    rc = rc ? rc : dalloc(c, &c->b, (size_t)c->stride);
+    rc = rc ? rc : dalloc(c, &c->slots, 3);
+    rc = rc ? rc : dalloc(c, &c->err, 1);
+    std::vector<int64_t> order;  // internal position -> caller cell
+    if (!rc && mesh->kind == SME_MESH_2D_TRI) {
+        TriGeom g;
+        rc = build_tri(c, mesh, g);
+        if (!rc) {
+            order = rcm_order(g.nbr, nc);
+            std::vector<int64_t> inv(nc);
+            for (int64_t k = 0; k < nc; ++k) inv[order[k]] = k;
+            std::vector<int32_t> nb(3 * c->stride, -1);
+            std::vector<double> fx(3 * c->stride, 0.0), fy(3 * c->stride, 0.0), fw(3 * c->stride, 0.0);
+            for (int64_t k = 0; k < nc; ++k) {
+                int64_t t = order[k];
+                for (int s = 0; s < 3; ++s) {
+                    int32_t v = g.nbr[3 * t + s];
+                    nb[s * c->stride + k] = v >= 0 ? (int32_t)inv[v] : -1;
+                    fx[s * c->stride + k] = g.nx[3 * t + s];
+                    fy[s * c->stride + k] = g.ny[3 * t + s];
+                    fw[s * c->stride + k] = g.w[3 * t + s];
+                }
+            }
+            rc = rc ? rc : dalloc(c, &c->nbr, 3 * c->stride);
+            rc = rc ? rc : dalloc(c, &c->fnx, 3 * c->stride);
+            rc = rc ? rc : dalloc(c, &c->fny, 3 * c->stride);
+            rc = rc ? rc : dalloc(c, &c->fw, 3 * c->stride);
+            rc = rc ? rc : dalloc(c, &c->to_internal, nc);
+            rc = rc ? rc : dalloc(c, &c->to_caller, nc);
+            if (!rc) {
+                hipError_t e = hipSuccess;
+                if (e == hipSuccess) e = hipMemcpy(c->nbr, nb.data(), nb.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+                if (e == hipSuccess) e = hipMemcpy(c->fnx, fx.data(), fx.size() * sizeof(double), hipMemcpyHostToDevice);
+                if (e == hipSuccess) e = hipMemcpy(c->fny, fy.data(), fy.size() * sizeof(double), hipMemcpyHostToDevice);
+                if (e == hipSuccess) e = hipMemcpy(c->fw, fw.data(), fw.size() * sizeof(double), hipMemcpyHostToDevice);
+                if (e == hipSuccess) e = hipMemcpy(c->to_internal, inv.data(), nc * sizeof(int64_t), hipMemcpyHostToDevice);
+                if (e == hipSuccess) e = hipMemcpy(c->to_caller, order.data(), nc * sizeof(int64_t), hipMemcpyHostToDevice);
+                if (e != hipSuccess) rc = fail(c, SME_EHIP, "geometry upload: %s", hipGetErrorString(e));
+            }
+        }
+    }
+    // bathymetry (caller order -> internal order)
+    if (!rc) {
+        hipError_t e = hipMemsetAsync(c->b, 0, c->stride * sizeof(double), c->stream);
+        if (e == hipSuccess && b) {
+            if (c->to_internal) {
+                double *tmp = c->q[1];
+                e = hipMemcpyAsync(tmp, b, nc * sizeof(double), b_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                                   c->stream);
+                if (e == hipSuccess) e = launch_permute(tmp, nc, c->b, c->stride, c->to_internal, nc, 1, c->stream);
+            } else {
+                e = hipMemcpyAsync(c->b, b, nc * sizeof(double), b_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                                   c->stream);
+            }
+        }
+        if (e == hipSuccess) e = hipMemsetAsync(c->q[0], 0, (size_t)nf * c->stride * sizeof(double), c->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(c->q[1], 0, (size_t)nf * c->stride * sizeof(double), c->stream);
+        if (e == hipSuccess) e = launch_slots_reset(c->slots, c->err, 0, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) rc = fail(c, SME_EHIP, "init upload: %s", hipGetErrorString(e));
+    }
+    if (rc) {
+        sme_destroy(c);
+        return rc;
+    }
+    *out = c;
+    return SME_OK;
+}
+
+int sme_set_state(sme_ctx *c, const double *q, int on_device)
+{
+    if (!c || !q) return SME_EINVAL;
+    const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    const size_t row = c->ncells * sizeof(double);
+    if (c->to_internal) {
+        double *tmp = c->q[1 - c->cur];
+        HIPCHK(c, hipMemcpy2DAsync(tmp, c->stride * sizeof(double), q, row, row, c->nf, kind, c->stream));
+        HIPCHK(c, launch_permute(tmp, c->stride, c->q[c->cur], c->stride, c->to_internal, c->ncells, c->nf, c->stream));
+    } else {
+        HIPCHK(c, hipMemcpy2DAsync(c->q[c->cur], c->stride * sizeof(double), q, row, row, c->nf, kind, c->stream));
+    }
+    // fresh clock and CFL ratio of the loaded state
+    c->sa = 0;
+    HIPCHK(c, launch_slots_reset(c->slots, c->err, 0, c->stream));
+    StepArgs a = make_args(c);
+    HIPCHK(c, launch_eig(c->kind == SME_MESH_1D ? 1 : 2, c->kind, c->level, a, c->stream));
+    c->has_state = true;
+    if (!on_device) HIPCHK(c, hipStreamSynchronize(c->stream));
+    return SME_OK;
+}
+
+int sme_get_state(sme_ctx *c, double *q, int on_device)
+{
+    if (!c || !q) return SME_EINVAL;
+    const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    const size_t row = c->ncells * sizeof(double);
+    const double *src = c->q[c->cur];
+    if (c->to_caller) {
+        double *tmp = c->q[1 - c->cur];
+        HIPCHK(c, launch_permute(src, c->stride, tmp, c->stride, c->to_caller, c->ncells, c->nf, c->stream));
+        src = tmp;
+    }
+    HIPCHK(c, hipMemcpy2DAsync(q, row, src, c->stride * sizeof(double), row, c->nf, kind, c->stream));
+    if (!on_device) HIPCHK(c, hipStreamSynchronize(c->stream));
+    return SME_OK;
+}
+
+int sme_eigmax(sme_ctx *c, double *lam_max, double *dt)
+{
+    if (!c) return SME_EINVAL;
+    if (!c->has_state) return fail(c, SME_EINVAL, "no state loaded");
+    HIPCHK(c, hipMemsetAsync(c->slots + c->sa, 0, 2 * sizeof(unsigned long long), c->stream));
+    StepArgs a = make_args(c);
+    HIPCHK(c, launch_eig(0, c->kind, c->level, a, c->stream));
+    Slot s;
+    int r = read_slot(c, &s, nullptr);
+    if (r) return r;
+    double rr, ll;
+    memcpy(&rr, &s.rbits, sizeof rr);
+    memcpy(&ll, &s.lbits, sizeof ll);
+    if (lam_max) *lam_max = ll;
+    if (dt) *dt = rr > 0 ? c->p.cfl / rr : 0.0;
+    return SME_OK;
+}
+
+int sme_step(sme_ctx *c, double dt, double *dt_used)
+{
+    if (!c) return SME_EINVAL;
+    if (!c->has_state) return fail(c, SME_EINVAL, "no state loaded");
+    if (std::isnan(dt)) return SME_EINVAL;
+    HIPCHK(c, launch_one_step(c, dt > 0 ? dt : 0.0, 0.0));
+    if (dt_used) {
+        Slot s;
+        int r = read_slot(c, &s, nullptr);
+        if (r) return r;
+        *dt_used = s.dt;
+    }
+    return SME_OK;
+}
+
+int sme_run(sme_ctx *c, int64_t n_steps, double t_end, double *t_out, int64_t *steps_done)
+{
+    if (!c || n_steps < 0 || std::isnan(t_end)) return SME_EINVAL;
+    if (!c->has_state) return fail(c, SME_EINVAL, "no state loaded");
+    const double te = t_end > 0 ? t_end : 0.0;
+    int64_t left = n_steps;
+    const bool use_graphs = getenv("SME_NO_GRAPH") == nullptr;
+    while (use_graphs && left >= kGraphSteps) {
+        hipGraphExec_t ex;
+        int r = get_graph(c, te, &ex);
+        if (r) return r;
+        HIPCHK(c, hipGraphLaunch(ex, c->stream));
+        left -= kGraphSteps;  // after six steps cur and slot are back where they started
+    }
+    while (left-- > 0) HIPCHK(c, launch_one_step(c, 0.0, te));
+    if (t_out || steps_done) {
+        Slot s;
+        ErrWord e;
+        int r = read_slot(c, &s, &e);
+        if (r) return r;
+        if (t_out) *t_out = s.t;
+        if (steps_done) *steps_done = s.step;
+        if (e.flag)
+            return fail(c, SME_ENONPHYS, "non-physical state (h <= 0 or non-finite) produced by step %llu",
+                        (unsigned long long)e.first_step);
+    }
+    return SME_OK;
+}
+
+int sme_time(sme_ctx *c, double *t, int64_t *steps)
+{
+    if (!c) return SME_EINVAL;
+    Slot s;
+    ErrWord e;
+    int r = read_slot(c, &s, &e);
+    if (r) return r;
+    if (t) *t = s.t;
+    if (steps) *steps = s.step;
+    if (e.flag)
+        return fail(c, SME_ENONPHYS, "non-physical state (h <= 0 or non-finite) produced by step %llu",
+                    (unsigned long long)e.first_step);
+    return SME_OK;
+}
+
+int sme_nfields(const sme_ctx *c) { return c ? c->nf : SME_EINVAL; }
+int64_t sme_ncells(const sme_ctx *c) { return c ? c->ncells : SME_EINVAL; }
+int sme_level(const sme_ctx *c) { return c ? c->level : SME_EINVAL; }
+const double *sme_state_device(const sme_ctx *c) { return c ? c->q[c->cur] : nullptr; }
+int64_t sme_field_stride(const sme_ctx *c) { return c ? c->stride : SME_EINVAL; }
+
+int sme_basis_tensors(int level, double *M, double *A, double *B, double *K)
+{
+    switch (level) {
+    case 0: copy_tensors<0>(M, A, B, K); return SME_OK;
+    case 1: copy_tensors<1>(M, A, B, K); return SME_OK;
+    case 2: copy_tensors<2>(M, A, B, K); return SME_OK;
+    case 3: copy_tensors<3>(M, A, B, K); return SME_OK;
+    case 4: copy_tensors<4>(M, A, B, K); return SME_OK;
+    case 5: copy_tensors<5>(M, A, B, K); return SME_OK;
+    case 6: copy_tensors<6>(M, A, B, K); return SME_OK;
+    case 7: copy_tensors<7>(M, A, B, K); return SME_OK;
+    case 8: copy_tensors<8>(M, A, B, K); return SME_OK;
+    default: return SME_EINVAL;
+    }
+}
+
+const char *sme_strerror(int code)
+{
+    switch (code) {
+    case SME_OK: return "ok";
+    case SME_EINVAL: return "invalid argument";
+    case SME_ENOMEM: return "out of memory";
+    case SME_EHIP: return "HIP runtime error";
+    case SME_ENONPHYS: return "non-physical state";
+    case SME_EMESH: return "invalid mesh";
+    default: return "unknown error";
+    }
+}
+
+const char *sme_last_error(const sme_ctx *c) { return c ? c->last.c_str() : "no context"; }
+
+void sme_destroy(sme_ctx *c)
+{
+    if (!c) return;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    drop_graphs(c);
+    (void)hipFree(c->q[0]);
+    (void)hipFree(c->q[1]);
+    (void)hipFree(c->b);
+    (void)hipFree(c->nbr);
+    (void)hipFree(c->fnx);
+    (void)hipFree(c->fny);
+    (void)hipFree(c->fw);
+    (void)hipFree(c->to_internal);
+    (void)hipFree(c->to_caller);
+    (void)hipFree(c->slots);
+    (void)hipFree(c->err);
+    if (c->own_stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,177 @@
+// sme_step_common.h -- device helpers shared by the step kernels.
+//
+// One launch per time step does the whole step for every cell:
+//   hyperbolic predictor  Q* = Q^n - dt/|V| sum_f |e_f| (Fhat_f + D_f / 2)   (Eq. (3a))
+//   friction ODE          Q^{n+1} = Q* + dt S(Q*)                           (Eq. (3d))
+//   CFL ratio of Q^{n+1}  r_i = sum_f |e_f| lam(Q_i, n_f) / (2 |V_i|), max-reduced
+// and the next launch reads dt = CFL / max r from the device (Sec. 3.1: adaptive
+// step), so a run needs no host round trip.
+//
+// Layouts: SoA FP64 state q[f * stride + cell].
+//   1D and structured 2D: a 64-lane wavefront owns 64 consecutive columns
+//   (62 outputs + one halo column each side).  Each lane computes the x-face to
+//   its right once; the left cell's share travels one lane up through a
+//   cross-lane shuffle.  In 2D the wave then marches up a strip of `rows` rows,
+//   keeping the previous row in registers, so every y-face is computed once too.
+//   Triangles: one lane per cell in a bandwidth-reducing (RCM) order, three
+//   neighbour gathers; each face is evaluated in a canonical orientation (from
+//   the lower to the higher cell index) so both neighbours see bitwise equal
+//   face values.
+// All reductions are wave shuffles plus one unsigned 64-bit atomic max per
+// wave on the bit pattern of a non-negative double: exact and order-free, so
+// runs are bitwise reproducible.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "sme_kernels.h"
+
+namespace sme {
+namespace detail {
+
+constexpr int kWave = 64;
+constexpr int kBlock = 256;
+constexpr int kOut = kWave - 2;  // outputs per wave along x
+
+__device__ __forceinline__ double step_dt(const StepArgs &a)
+{
+    const Slot &sl = a.slots[a.sa];
+    double dt;
+    if (a.dt_fixed > 0.0) {
+        dt = a.dt_fixed;
+    } else {
+        double r = __longlong_as_double((long long)sl.rbits);
+        dt = r > 0.0 ? a.cfl / r : 0.0;
+    }
+    if (a.t_end > 0.0) dt = fmin(dt, fmax(a.t_end - sl.t, 0.0));
+    return dt;
+}
+
+// bookkeeping of the time slots, done by one lane of the grid
+__device__ __forceinline__ void slot_update(const StepArgs &a, double dt)
+{
+    const Slot &sl = a.slots[a.sa];
+    Slot &nx = a.slots[a.sb];
+    nx.t = sl.t + dt;
+    nx.dt = dt;
+    nx.step = sl.step + (dt > 0.0 ? 1 : 0);
+    a.slots[a.sc].rbits = 0ull;
+    a.slots[a.sc].lbits = 0ull;
+}
+
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, kWave));
+    return v;
+}
+
+__device__ __forceinline__ void publish_max(unsigned long long *dst, double v)
+{
+    v = wave_max(v);
+    if ((threadIdx.x & (kWave - 1)) == 0 && v > 0.0)
+        atomicMax(dst, (unsigned long long)__double_as_longlong(v));
+}
+
+__device__ __forceinline__ void flag_bad(const StepArgs &a, bool bad)
+{
+    if (bad) {
+        atomicOr(&a.err->flag, 1u);
+        atomicMin(&a.err->first_step, (unsigned long long)(a.slots[a.sa].step + 1));
+    }
+}
+
+template <int N>
+__device__ __forceinline__ double lam_of(double g, double h, double ih, const double *q)
+{
+    double a[N + 1];
+#pragma unroll
+    for (int k = 0; k <= N; ++k) a[k] = q[k] * ih;
+    return lam_bound<N>(g * h, a);
+}
+
+// CFL ratio r_i = sum_f |e_f| lam(Q_i, n_f) / (2 |V_i|) of one cell (the same
+// expression in the step epilogue and in the stand-alone reduction, so a state
+// reloaded from a checkpoint continues bitwise identically).
+template <int N>
+__device__ __forceinline__ double cfl_ratio_1d(double g, double h, double ih, const double *q, double idx,
+                                               double *lmax)
+{
+    double l = lam_of<N>(g, h, ih, q);
+    *lmax = l;
+    return l * idx;
+}
+
+template <int N>
+__device__ __forceinline__ double cfl_ratio_2d(double g, double h, double ih, const double *qx, const double *qy,
+                                               double idx, double idy, double *lmax)
+{
+    double lx = lam_of<N>(g, h, ih, qx), ly = lam_of<N>(g, h, ih, qy);
+    *lmax = fmax(lx, ly);
+    return lx * idx + ly * idy;
+}
+
+template <int N>
+__device__ __forceinline__ double cfl_ratio_tri(double g, double h, double ih, const double *qx, const double *qy,
+                                                const double *fnx, const double *fny, const double *fw,
+                                                double *lmax)
+{
+    const double gh = g * h;
+    double r = 0.0, lm = 0.0;
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+        double an[N + 1];
+#pragma unroll
+        for (int k = 0; k <= N; ++k) an[k] = fma(qx[k], fnx[s], qy[k] * fny[s]) * ih;
+        double l = lam_bound<N>(gh, an);
+        lm = fmax(lm, l);
+        r = fma(0.5 * fw[s], l, r);
+    }
+    *lmax = lm;
+    return r;
+}
+
+template <typename T>
+__device__ __forceinline__ T shfl_dn(T v) { return __shfl_down(v, 1, kWave); }
+template <typename T>
+__device__ __forceinline__ T shfl_up1(T v) { return __shfl_up(v, 1, kWave); }
+
+// Source column / row for a (possibly ghost) index along one axis.
+// Returns the index to load and whether the normal momenta are mirrored.
+__device__ __forceinline__ int ghost_index(int c, int n, int bc_lo, int bc_hi, bool &mirror)
+{
+    mirror = false;
+    if (c < 0) {
+        if (bc_lo == BC_PERIODIC) return n - 1;
+        mirror = (bc_lo == BC_WALL);
+        return 0;
+    }
+    if (c >= n) {
+        if (c == n) {
+            if (bc_hi == BC_PERIODIC) return 0;
+            mirror = (bc_hi == BC_WALL);
+        }
+        return n - 1;
+    }
+    return c;
+}
+
+inline unsigned blocks_for(int64_t threads) { return (unsigned)((threads + kBlock - 1) / kBlock); }
+
+}  // namespace detail
+}  // namespace sme
+
+#define SME_LEVEL_SWITCH(level, CALL) \
+    switch (level) {                  \
+    case 0: CALL(0); break;           \
+    case 1: CALL(1); break;           \
+    case 2: CALL(2); break;           \
+    case 3: CALL(3); break;           \
+    case 4: CALL(4); break;           \
+    case 5: CALL(5); break;           \
+    case 6: CALL(6); break;           \
+    case 7: CALL(7); break;           \
+    case 8: CALL(8); break;           \
+    default: return hipErrorInvalidValue; \
+    }
+

@@ -1,0 +1,260 @@
+"""Python binding of the SME HIP library (``libsme.so``, C ABI in include/sme.h).
+
+Argument marshalling only: every step of the method runs in the library's HIP
+kernels.  The functions carry the C names.  Device buffers may be torch CUDA
+tensors (torch provides device memory and streams); host buffers are numpy
+arrays.  ``torch`` is imported before the library is loaded so that both use the
+one HIP runtime torch ships with.
+
+If ``libsme.so`` has not been built, importing this module raises ImportError:
+there is no fallback path.
+"""
+import ctypes
+import os
+
+import numpy as np
+import torch  # noqa: F401  (must precede loading libsme.so: one HIP runtime per process)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsme.so")
+
+SME_OK, SME_EINVAL, SME_ENOMEM, SME_EHIP, SME_ENONPHYS, SME_EMESH = 0, -1, -2, -3, -4, -5
+SME_MESH_1D, SME_MESH_2D_STRUCT, SME_MESH_2D_TRI = 1, 2, 3
+SME_BC_PERIODIC, SME_BC_EXTRAP, SME_BC_WALL = 0, 1, 2
+BC = {"periodic": SME_BC_PERIODIC, "extrap": SME_BC_EXTRAP, "wall": SME_BC_WALL}
+MAX_LEVEL = 8
+
+EXPORTS = [
+    "sme_layout", "sme_init", "sme_set_state", "sme_get_state", "sme_eigmax", "sme_step",
+    "sme_run", "sme_time", "sme_nfields", "sme_ncells", "sme_level", "sme_state_device",
+    "sme_field_stride",
+    "sme_basis_tensors", "sme_strerror", "sme_last_error", "sme_destroy",
+]
+
+
+class sme_params(ctypes.Structure):
+    _fields_ = [("g", ctypes.c_double), ("c_slip", ctypes.c_double), ("nu", ctypes.c_double),
+                ("cfl", ctypes.c_double), ("quad_points", ctypes.c_int)]
+
+
+class sme_mesh(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("nx", ctypes.c_int64), ("ny", ctypes.c_int64),
+                ("x0", ctypes.c_double), ("x1", ctypes.c_double), ("y0", ctypes.c_double),
+                ("y1", ctypes.c_double), ("bc", ctypes.c_int * 4), ("n_vert", ctypes.c_int64),
+                ("n_tri", ctypes.c_int64), ("vert_xy", ctypes.c_void_p), ("tri", ctypes.c_void_p)]
+
+
+class SmeError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (code {code})")
+        self.code = code
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run paper_2601_04826_amd.build.build() "
+                          "(there is no CPU fallback)")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i64, d, i = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int
+    P = ctypes.POINTER
+    sig = {
+        "sme_layout": (i, [i, vp, P(i), P(i64)]),
+        "sme_init": (i, [P(vp), i, vp, vp, vp, i, vp]),
+        "sme_set_state": (i, [vp, vp, i]),
+        "sme_get_state": (i, [vp, vp, i]),
+        "sme_eigmax": (i, [vp, P(d), P(d)]),
+        "sme_step": (i, [vp, d, P(d)]),
+        "sme_run": (i, [vp, i64, d, P(d), P(i64)]),
+        "sme_time": (i, [vp, P(d), P(i64)]),
+        "sme_nfields": (i, [vp]),
+        "sme_ncells": (i64, [vp]),
+        "sme_level": (i, [vp]),
+        "sme_state_device": (vp, [vp]),
+        "sme_field_stride": (i64, [vp]),
+        "sme_basis_tensors": (i, [i, vp, vp, vp, vp]),
+        "sme_strerror": (ctypes.c_char_p, [i]),
+        "sme_last_error": (ctypes.c_char_p, [vp]),
+        "sme_destroy": (None, [vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+_lib = _load()
+
+
+def lib():
+    return _lib
+
+
+def _check(code, ctx=None):
+    if code != SME_OK:
+        msg = _lib.sme_strerror(code).decode()
+        if ctx:
+            detail = _lib.sme_last_error(ctx).decode()
+            if detail:
+                msg = f"{msg}: {detail}"
+        raise SmeError(code, msg)
+
+
+def _ptr(a):
+    if isinstance(a, torch.Tensor):
+        return ctypes.c_void_p(a.data_ptr()), bool(a.is_cuda)
+    return a.ctypes.data_as(ctypes.c_void_p), False
+
+
+def make_params(g=9.81, c_slip=0.0, nu=0.0, cfl=0.45, quad_points=3):
+    return sme_params(g, c_slip, nu, cfl, quad_points)
+
+
+def make_mesh(problem):
+    """sme_mesh for a workload description (see ``workloads``); returns (mesh, keepalive)."""
+    m = sme_mesh()
+    k = problem["kind"]
+    keep = []
+    if k in ("1d", "2d"):
+        m.kind = SME_MESH_1D if k == "1d" else SME_MESH_2D_STRUCT
+        m.nx, m.ny = problem["nx"], problem.get("ny", 1)
+        m.x0, m.x1 = problem["x0"], problem["x1"]
+        m.y0, m.y1 = problem.get("y0", 0.0), problem.get("y1", 1.0)
+        bc = list(problem["bc"]) + ["periodic"] * (4 - len(problem["bc"]))
+        for s in range(4):
+            m.bc[s] = BC[bc[s]]
+    elif k == "tri":
+        vert = np.ascontiguousarray(problem["vert"], dtype=np.float64)
+        tri = np.ascontiguousarray(problem["tri"], dtype=np.int32)
+        keep = [vert, tri]
+        m.kind = SME_MESH_2D_TRI
+        m.n_vert, m.n_tri = vert.shape[0], tri.shape[0]
+        m.vert_xy = vert.ctypes.data_as(ctypes.c_void_p)
+        m.tri = tri.ctypes.data_as(ctypes.c_void_p)
+    else:
+        raise ValueError(k)
+    return m, keep
+
+
+def sme_layout(level, mesh):
+    nf, nc = ctypes.c_int(), ctypes.c_int64()
+    _check(_lib.sme_layout(level, ctypes.byref(mesh), ctypes.byref(nf), ctypes.byref(nc)))
+    return nf.value, nc.value
+
+
+def sme_init(level, mesh, params, b=None, stream=None):
+    ctx = ctypes.c_void_p()
+    if b is not None:
+        if not isinstance(b, torch.Tensor):
+            b = np.ascontiguousarray(b, dtype=np.float64)
+        bp, bdev = _ptr(b)
+    else:
+        bp, bdev = None, False
+    if stream is None and torch.cuda.is_available():
+        stream = torch.cuda.current_stream().cuda_stream
+    _check(_lib.sme_init(ctypes.byref(ctx), level, ctypes.byref(mesh), ctypes.byref(params), bp,
+                         int(bdev), ctypes.c_void_p(stream or 0)))
+    return ctx
+
+
+def sme_set_state(ctx, q):
+    if isinstance(q, torch.Tensor):
+        q = q.contiguous()
+        if q.dtype != torch.float64:
+            raise TypeError("state must be float64")
+    else:
+        q = np.ascontiguousarray(q, dtype=np.float64)
+    p, dev = _ptr(q)
+    _check(_lib.sme_set_state(ctx, p, int(dev)), ctx)
+
+
+def sme_get_state(ctx, out=None):
+    nf, nc = _lib.sme_nfields(ctx), _lib.sme_ncells(ctx)
+    if out is None:
+        out = np.empty((nf, nc))
+    p, dev = _ptr(out)
+    _check(_lib.sme_get_state(ctx, p, int(dev)), ctx)
+    return out
+
+
+def sme_eigmax(ctx):
+    lam, dt = ctypes.c_double(), ctypes.c_double()
+    _check(_lib.sme_eigmax(ctx, ctypes.byref(lam), ctypes.byref(dt)), ctx)
+    return lam.value, dt.value
+
+
+def sme_step(ctx, dt=0.0, sync=False):
+    used = ctypes.c_double()
+    _check(_lib.sme_step(ctx, float(dt), ctypes.byref(used) if sync else None), ctx)
+    return used.value if sync else None
+
+
+def sme_run(ctx, n_steps, t_end=0.0, sync=True):
+    t, s = ctypes.c_double(), ctypes.c_int64()
+    if sync:
+        _check(_lib.sme_run(ctx, int(n_steps), float(t_end), ctypes.byref(t), ctypes.byref(s)), ctx)
+        return t.value, s.value
+    _check(_lib.sme_run(ctx, int(n_steps), float(t_end), None, None), ctx)
+    return None
+
+
+def sme_time(ctx):
+    t, s = ctypes.c_double(), ctypes.c_int64()
+    _check(_lib.sme_time(ctx, ctypes.byref(t), ctypes.byref(s)), ctx)
+    return t.value, s.value
+
+
+def sme_destroy(ctx):
+    _lib.sme_destroy(ctx)
+
+
+def sme_basis_tensors(level):
+    n = level + 1
+    M, A, B, K = np.zeros(n), np.zeros(n ** 3), np.zeros(n ** 3), np.zeros(n * n)
+    _check(_lib.sme_basis_tensors(level, *(x.ctypes.data_as(ctypes.c_void_p) for x in (M, A, B, K))))
+    return {"M": M, "A": A.reshape(n, n, n), "B": B.reshape(n, n, n), "K": K.reshape(n, n)}
+
+
+class Solver:
+    """One SME context: ``Solver(problem)`` builds it from a workload description."""
+
+    def __init__(self, problem, stream=None, **param_overrides):
+        p = dict(problem["params"])
+        p.update(param_overrides)
+        self.problem = problem
+        self.level = problem["level"]
+        self.params = make_params(**p)
+        self.mesh, keep = make_mesh(problem)
+        self.ctx = sme_init(self.level, self.mesh, self.params, problem.get("b"), stream)
+        del keep
+        self.nf = _lib.sme_nfields(self.ctx)
+        self.ncells = _lib.sme_ncells(self.ctx)
+
+    def set_state(self, q):
+        sme_set_state(self.ctx, q)
+
+    def get_state(self, out=None):
+        return sme_get_state(self.ctx, out)
+
+    def eigmax(self):
+        return sme_eigmax(self.ctx)
+
+    def step(self, dt=0.0, sync=False):
+        return sme_step(self.ctx, dt, sync)
+
+    def run(self, n_steps, t_end=0.0, sync=True):
+        return sme_run(self.ctx, n_steps, t_end, sync)
+
+    def time(self):
+        return sme_time(self.ctx)
+
+    def close(self):
+        if self.ctx:
+            sme_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

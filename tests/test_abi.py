@@ -1,0 +1,70 @@
+"""CPU checks of the C ABI library: it loads, exports every symbol that
+include/sme.h declares, validates meshes, and carries the basis tensors the
+oracle computes independently (no GPU work is launched here)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import tensors as T
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sme.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(sme_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def sme():
+    from paper_2601_04826_amd import sme as m
+
+    return m
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for must in ("sme_init", "sme_step", "sme_run", "sme_eigmax", "sme_set_state", "sme_get_state",
+                 "sme_destroy"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(sme):
+    lib = ctypes.CDLL(sme.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+    assert sorted(sme.EXPORTS) == declared_functions()
+
+
+@pytest.mark.parametrize("level", range(0, 9))
+def test_library_tensors_equal_exact_rationals(sme, level):
+    got = sme.sme_basis_tensors(level)
+    want = T.tensors(level)
+    for key in ("M", "A", "B", "K"):
+        np.testing.assert_allclose(got[key], want[key], rtol=2.3e-16, atol=0)
+
+
+def test_layout_and_validation(sme):
+    m, _ = sme.make_mesh(dict(kind="2d", nx=10, ny=7, x0=0, x1=1, y0=0, y1=1, bc=("wall",) * 4))
+    assert sme.sme_layout(3, m) == (9, 70)
+    m1, _ = sme.make_mesh(dict(kind="1d", nx=12, x0=0, x1=1, bc=("extrap", "extrap")))
+    assert sme.sme_layout(8, m1) == (10, 12)
+    with pytest.raises(sme.SmeError) as e:
+        sme.sme_layout(9, m)
+    assert e.value.code == sme.SME_EINVAL
+    bad, _ = sme.make_mesh(dict(kind="1d", nx=12, x0=0, x1=1, bc=("periodic", "extrap")))
+    with pytest.raises(sme.SmeError):
+        sme.sme_layout(1, bad)
+    vert = np.array([[0.0, 0.0], [1.0, 0.0], [0.0, 1.0]])
+    t, _ = sme.make_mesh(dict(kind="tri", vert=vert, tri=np.array([[0, 1, 2]], dtype=np.int32)))
+    assert sme.sme_layout(2, t) == (7, 1)
+
+
+def test_strerror(sme):
+    assert sme.lib().sme_strerror(sme.SME_ENONPHYS) == b"non-physical state"
+    assert sme.lib().sme_strerror(0) == b"ok"
