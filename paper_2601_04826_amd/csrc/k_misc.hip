@@ -40,6 +40,11 @@ __global__ __launch_bounds__(kBlock) void k_eig(StepArgs a)
             }
             r = cfl_ratio_tri<N>(a.g, h, ih, qx, qy, fnx, fny, fw, &lmax);
         }
+        // a loaded state must be physical too (step index = current step count)
+        bool bad = !(h > 0.0) || !isfinite(h);
+#pragma unroll
+        for (int k = 0; k < n; ++k) bad |= !isfinite(qx[k]) || !isfinite(qy[k]);
+        flag_bad_at(a, bad, a.slots[a.sa].step);
         if (!(r >= 0.0)) r = 0.0;
         if (!(lmax >= 0.0)) lmax = 0.0;
     }

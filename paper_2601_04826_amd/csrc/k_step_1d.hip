@@ -20,62 +20,62 @@ __global__ __launch_bounds__(kBlock) void k_step_1d(StepArgs a)
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = (blockIdx.x * kBlock + threadIdx.x) >> 6;
     const int x0 = wave * kOut;
-    if (x0 >= a.nx) return;  // whole wave beyond the grid
-    const int c = x0 - 1 + lane;
-    bool mir;
-    const int src = ghost_index(c, a.nx, a.bc[0], a.bc[1], mir);
-    const bool out = lane >= 1 && lane <= kOut && c < a.nx;
-
-    Side<N, false> S;
-    S.h = a.q[src];
-    S.b = a.b[src];
-#pragma unroll
-    for (int k = 0; k < n; ++k) {
-        double v = a.q[(1 + k) * a.stride + src];
-        S.qa[k] = mir ? -v : v;
-    }
-    side_flux<N, false>(S, a.g);
-
-    Side<N, false> R;
-    R.h = shfl_dn(S.h);
-    R.b = shfl_dn(S.b);
-    R.Fh = shfl_dn(S.Fh);
-    R.lam = shfl_dn(S.lam);
-#pragma unroll
-    for (int k = 0; k < n; ++k) {
-        R.qa[k] = shfl_dn(S.qa[k]);
-        R.Fa[k] = shfl_dn(S.Fa[k]);
-    }
-    double Fh[1 + n], D[1 + n];
-    face_flux<N, false>(S, R, a.g, a.quad, Fh, D);
-    double acc[1 + n];
-#pragma unroll
-    for (int f = 0; f < 1 + n; ++f) {
-        double own = fma(0.5, D[f], Fh[f]);
-        double oth = fma(0.5, D[f], -Fh[f]);
-        acc[f] = own + shfl_up1(oth);
-    }
-    // predictor and friction
-    const double sc = dt * a.idx;
-    double h = fma(-sc, acc[0], S.h);
-    double q[n];
-#pragma unroll
-    for (int k = 0; k < n; ++k) q[k] = fma(-sc, acc[1 + k], S.qa[k]);
-    const double ih = rcp(h);
-    friction<N>(q, ih, dt, a.c_slip, a.nu);
     double r = 0.0;
-    if (out) {
-        a.qn[c] = h;
-        bool bad = !(h > 0.0) || !isfinite(h);
+    if (x0 < a.nx) {  // waves beyond the grid only join the reduction
+        const int c = x0 - 1 + lane;
+        bool mir;
+        const int src = ghost_index(c, a.nx, a.bc[0], a.bc[1], mir);
+        const bool out = lane >= 1 && lane <= kOut && c < a.nx;
+
+        Side<N, false> S;
+        S.h = a.q[src];
+        S.b = a.b[src];
 #pragma unroll
         for (int k = 0; k < n; ++k) {
-            a.qn[(1 + k) * a.stride + c] = q[k];
-            bad |= !isfinite(q[k]);
+            double v = a.q[(1 + k) * a.stride + src];
+            S.qa[k] = mir ? -v : v;
         }
-        flag_bad(a, bad);
-        double lm;
-        r = cfl_ratio_1d<N>(a.g, h, ih, q, a.idx, &lm);
-        if (!(r >= 0.0)) r = 0.0;
+        side_flux<N, false>(S, a.g);
+
+        Side<N, false> R;
+        R.h = shfl_dn(S.h);
+        R.b = shfl_dn(S.b);
+        R.lam = shfl_dn(S.lam);
+#pragma unroll
+        for (int k = 0; k < n; ++k) {
+            R.qa[k] = shfl_dn(S.qa[k]);
+            R.Fa[k] = shfl_dn(S.Fa[k]);
+        }
+        double Fh[1 + n], D[1 + n];
+        face_flux<N, false>(S, R, a.g, a.quad, Fh, D);
+        double acc[1 + n];
+#pragma unroll
+        for (int f = 0; f < 1 + n; ++f) {
+            double own = fma(0.5, D[f], Fh[f]);
+            double oth = fma(0.5, D[f], -Fh[f]);
+            acc[f] = own + shfl_up1(oth);
+        }
+        // predictor and friction
+        const double sc = dt * a.idx;
+        double h = fma(-sc, acc[0], S.h);
+        double q[n];
+#pragma unroll
+        for (int k = 0; k < n; ++k) q[k] = fma(-sc, acc[1 + k], S.qa[k]);
+        const double ih = rcp(h);
+        friction<N>(q, ih, dt, a.c_slip, a.nu);
+        if (out) {
+            a.qn[c] = h;
+            bool bad = !(h > 0.0) || !isfinite(h);
+#pragma unroll
+            for (int k = 0; k < n; ++k) {
+                a.qn[(1 + k) * a.stride + c] = q[k];
+                bad |= !isfinite(q[k]);
+            }
+            flag_bad(a, bad);
+            double lm;
+            r = cfl_ratio_1d<N>(a.g, h, ih, q, a.idx, &lm);
+            if (!(r >= 0.0)) r = 0.0;
+        }
     }
     publish_max(&a.slots[a.sb].rbits, r);
 }

@@ -1,4 +1,16 @@
 // k_step_2d.hip -- SME step on structured 2D grids (one launch per step).
+//
+// Fields (h, qx_0..qx_N, qy_0..qy_N), cell index j * nx + i.  A 64-lane wave
+// owns 64 consecutive columns (62 outputs and one halo column on each side) of
+// a band of `rows` rows and marches up the band:
+//   * each cell's flux is evaluated once for both directions; the x-frame and
+//     y-frame tangential blocks are the same quadratic form (A is symmetric);
+//   * each lane computes the x-face to its right; the right cell's share moves
+//     one lane up through a cross-lane shuffle;
+//   * the y-face between the previous and the current row is computed once,
+//     with the previous row held in registers (two register sets that swap
+//     roles every row, so nothing is copied);
+//   * the next row's loads are issued before the current row is computed.
 #include <hip/hip_runtime.h>
 
 #include "sme_step_common.h"
@@ -9,36 +21,184 @@ using namespace detail;
 
 namespace {
 
-// ----------------------------------------------------------------------------
-// Structured 2D: fields (h, qx_0..qx_N, qy_0..qy_N), cell index j * nx + i.
 template <int N>
-__device__ __forceinline__ void load_2d(const StepArgs &a, int64_t cell, bool mx, bool my, double &h,
-                                        double &b, double *qx, double *qy)
+struct Cell2 {
+    static constexpr int n = N + 1;
+    double h, b;
+    double qx[n], qy[n];  // state as loaded (ghosts mirrored)
+    double Fxx[n];        // x-frame normal block (x momenta), gravity included
+    double Fyy[n];        // y-frame normal block (y momenta), gravity included
+    double Ft[n];         // tangential block, identical in both frames
+    double lx, ly;        // wave-speed bounds along x and y
+};
+
+template <int N>
+struct Raw2 {
+    double h, b;
+    double qx[N + 1], qy[N + 1];
+};
+
+template <int N>
+__device__ __forceinline__ void load_raw(const StepArgs &a, int row, bool my, int col, bool mx, Raw2<N> &r)
 {
     constexpr int n = N + 1;
-    h = a.q[cell];
-    b = a.b[cell];
+    const int64_t cell = (int64_t)row * a.nx + col;
+    r.h = a.q[cell];
+    r.b = a.b[cell];
 #pragma unroll
     for (int k = 0; k < n; ++k) {
-        double vx = a.q[(1 + k) * a.stride + cell];
-        double vy = a.q[(1 + n + k) * a.stride + cell];
-        qx[k] = mx ? -vx : vx;
-        qy[k] = my ? -vy : vy;
+        const double vx = a.q[(1 + k) * a.stride + cell];
+        const double vy = a.q[(1 + n + k) * a.stride + cell];
+        r.qx[k] = mx ? -vx : vx;
+        r.qy[k] = my ? -vy : vy;
     }
 }
 
-// finish one cell: predictor, friction, store, CFL ratio of the new state
 template <int N>
-__device__ __forceinline__ double finish_2d(const StepArgs &a, double dt, int64_t cell, bool out, double h0,
-                                            const double *qx0, const double *qy0, const double *acc)
+__device__ __forceinline__ void load_row(const StepArgs &a, int j, int col, bool mx, Raw2<N> &r)
+{
+    bool my;
+    const int row = ghost_index(j, a.ny, a.bc[2], a.bc[3], my);
+    load_raw<N>(a, row, my, col, mx, r);
+}
+
+template <int N>
+__device__ __forceinline__ void cell_flux(Cell2<N> &c, const Raw2<N> &r, double g)
 {
     constexpr int n = N + 1;
-    double h = fma(-dt, acc[0], h0);
+    c.h = r.h;
+    c.b = r.b;
+#pragma unroll
+    for (int k = 0; k < n; ++k) {
+        c.qx[k] = r.qx[k];
+        c.qy[k] = r.qy[k];
+    }
+    const double ih = rcp(c.h);
+    double al[n], be[n];
+#pragma unroll
+    for (int k = 0; k < n; ++k) {
+        al[k] = c.qx[k] * ih;
+        be[k] = c.qy[k] * ih;
+    }
+    double fxx[n], fyy[n], ft[n];
+    quad_form<N>(c.qx, al, fxx);
+    quad_form<N>(c.qy, be, fyy);
+    quad_form<N>(c.qx, be, ft);
+#pragma unroll
+    for (int k = 0; k < n; ++k) {
+        c.Fxx[k] = fxx[k] * Basis<N>::T.invM[k];
+        c.Fyy[k] = fyy[k] * Basis<N>::T.invM[k];
+        c.Ft[k] = ft[k] * Basis<N>::T.invM[k];
+    }
+    const double gh = g * c.h;
+    const double p = 0.5 * gh * c.h;
+    c.Fxx[0] += p;
+    c.Fyy[0] += p;
+    c.lx = lam_bound<N>(gh, al);
+    c.ly = lam_bound<N>(gh, be);
+}
+
+template <int N>
+__device__ __forceinline__ void x_side(const Cell2<N> &c, Side<N, true> &s)
+{
+    s.h = c.h;
+    s.b = c.b;
+#pragma unroll
+    for (int k = 0; k <= N; ++k) {
+        s.qa[k] = c.qx[k];
+        s.qt[k] = c.qy[k];
+        s.Fa[k] = c.Fxx[k];
+        s.Ft[k] = c.Ft[k];
+    }
+    s.lam = c.lx;
+}
+
+template <int N>
+__device__ __forceinline__ void y_side(const Cell2<N> &c, Side<N, true> &s)
+{
+    s.h = c.h;
+    s.b = c.b;
+#pragma unroll
+    for (int k = 0; k <= N; ++k) {
+        s.qa[k] = c.qy[k];
+        s.qt[k] = c.qx[k];
+        s.Fa[k] = c.Fyy[k];
+        s.Ft[k] = c.Ft[k];
+    }
+    s.lam = c.ly;
+}
+
+// y-face between P (below) and C (above), normal +y.  Adds P's share to accP
+// and sets accC to C's share; both in physical field order, scaled by 1/dy.
+template <int N>
+__device__ __forceinline__ void y_face(const StepArgs &a, const Cell2<N> &P, const Cell2<N> &C, double *accP,
+                                       double *accC, bool add_p)
+{
+    constexpr int n = N + 1;
+    Side<N, true> L, R;
+    y_side<N>(P, L);
+    y_side<N>(C, R);
+    double Fh[2 * n + 1], D[2 * n + 1];
+    face_flux<N, true>(L, R, a.g, a.quad, Fh, D);
+    // frame [h, y.., x..] -> physical [h, x.., y..]
+    if (add_p) {
+        accP[0] = fma(a.idy, fma(0.5, D[0], Fh[0]), accP[0]);
+#pragma unroll
+        for (int k = 0; k < n; ++k) {
+            accP[1 + n + k] = fma(a.idy, fma(0.5, D[1 + k], Fh[1 + k]), accP[1 + n + k]);
+            accP[1 + k] = fma(a.idy, fma(0.5, D[1 + n + k], Fh[1 + n + k]), accP[1 + k]);
+        }
+    }
+    if (accC) {
+        accC[0] = a.idy * fma(0.5, D[0], -Fh[0]);
+#pragma unroll
+        for (int k = 0; k < n; ++k) {
+            accC[1 + n + k] = a.idy * fma(0.5, D[1 + k], -Fh[1 + k]);
+            accC[1 + k] = a.idy * fma(0.5, D[1 + n + k], -Fh[1 + n + k]);
+        }
+    }
+}
+
+// x-faces of the row of C: face to the right of each lane, neighbour via shuffle.
+template <int N>
+__device__ __forceinline__ void x_faces(const StepArgs &a, const Cell2<N> &C, double *accC)
+{
+    constexpr int n = N + 1;
+    constexpr int nf = 2 * n + 1;
+    Side<N, true> X, R;
+    x_side<N>(C, X);
+    R.h = shfl_dn(X.h);
+    R.b = shfl_dn(X.b);
+    R.lam = shfl_dn(X.lam);
+#pragma unroll
+    for (int k = 0; k < n; ++k) {
+        R.qa[k] = shfl_dn(X.qa[k]);
+        R.qt[k] = shfl_dn(X.qt[k]);
+        R.Fa[k] = shfl_dn(X.Fa[k]);
+        R.Ft[k] = shfl_dn(X.Ft[k]);
+    }
+    double Gh[nf], E[nf];
+    face_flux<N, true>(X, R, a.g, a.quad, Gh, E);
+#pragma unroll
+    for (int f = 0; f < nf; ++f) {
+        const double own = fma(0.5, E[f], Gh[f]);
+        const double oth = fma(0.5, E[f], -Gh[f]);
+        accC[f] = fma(a.idx, own + shfl_up1(oth), accC[f]);
+    }
+}
+
+// predictor, friction, store, CFL ratio of the new state
+template <int N>
+__device__ __forceinline__ double finish_cell(const StepArgs &a, double dt, int64_t cell, bool out,
+                                              const Cell2<N> &c, const double *acc)
+{
+    constexpr int n = N + 1;
+    const double h = fma(-dt, acc[0], c.h);
     double qx[n], qy[n];
 #pragma unroll
     for (int k = 0; k < n; ++k) {
-        qx[k] = fma(-dt, acc[1 + k], qx0[k]);
-        qy[k] = fma(-dt, acc[1 + n + k], qy0[k]);
+        qx[k] = fma(-dt, acc[1 + k], c.qx[k]);
+        qy[k] = fma(-dt, acc[1 + n + k], c.qy[k]);
     }
     const double ih = rcp(h);
     friction<N>(qx, ih, dt, a.c_slip, a.nu);
@@ -46,19 +206,43 @@ __device__ __forceinline__ double finish_2d(const StepArgs &a, double dt, int64_
     double r = 0.0;
     if (out) {
         a.qn[cell] = h;
-        bool bad = !(h > 0.0) || !isfinite(h);
+        double sum = h;
 #pragma unroll
         for (int k = 0; k < n; ++k) {
             a.qn[(1 + k) * a.stride + cell] = qx[k];
             a.qn[(1 + n + k) * a.stride + cell] = qy[k];
-            bad |= !isfinite(qx[k]) || !isfinite(qy[k]);
+            sum += qx[k] + qy[k];
         }
-        flag_bad(a, bad);
+        flag_bad(a, !(h > 0.0) || !isfinite(sum));
         double lm;
         r = cfl_ratio_2d<N>(a.g, h, ih, qx, qy, a.idx, a.idy, &lm);
         if (!(r >= 0.0)) r = 0.0;
     }
     return r;
+}
+
+// one row: C <- row j (state in `raw`), y-face with P, finish P (row j-1) if
+// requested, x-faces of C.
+template <int N>
+__device__ __forceinline__ void row(const StepArgs &a, double dt, Cell2<N> &P, double *accP, Cell2<N> &C,
+                                    double *accC, const Raw2<N> &raw, int j, int c, bool outc, bool finish_p,
+                                    double &rmax)
+{
+    cell_flux<N>(C, raw, a.g);
+    y_face<N>(a, P, C, accP, accC, finish_p);
+    if (finish_p) rmax = fmax(rmax, finish_cell<N>(a, dt, (int64_t)(j - 1) * a.nx + c, outc, P, accP));
+    x_faces<N>(a, C, accC);
+}
+
+// closing y-face of the band: P is the last row (j1 - 1), raw the row above
+template <int N>
+__device__ __forceinline__ void close_band(const StepArgs &a, double dt, Cell2<N> &P, double *accP,
+                                           Cell2<N> &G, const Raw2<N> &raw, int j1, int c, bool outc,
+                                           double &rmax)
+{
+    cell_flux<N>(G, raw, a.g);
+    y_face<N>(a, P, G, accP, nullptr, true);
+    rmax = fmax(rmax, finish_cell<N>(a, dt, (int64_t)(j1 - 1) * a.nx + c, outc, P, accP));
 }
 
 template <int N>
@@ -72,118 +256,42 @@ __global__ __launch_bounds__(kBlock) void k_step_2d(StepArgs a)
     const int wave = (blockIdx.x * kBlock + threadIdx.x) >> 6;
     const int nsx = (a.nx + kOut - 1) / kOut;
     const int nsy = (a.ny + a.rows - 1) / a.rows;
-    if (wave >= nsx * nsy) return;
-    const int sx = wave % nsx;
-    const int sy = wave / nsx;
-    const int c = sx * kOut - 1 + lane;
-    const int j0 = sy * a.rows;
-    const int j1 = min(j0 + a.rows, a.ny);
-    bool mx;
-    const int col = ghost_index(c, a.nx, a.bc[0], a.bc[1], mx);
-    const bool outc = lane >= 1 && lane <= kOut && c < a.nx;
-
-    // previous row, y-frame: qa = qy, qt = qx
-    Side<N, true> P;
-    double accP[nf];
-    {
-        bool my;
-        const int row = ghost_index(j0 - 1, a.ny, a.bc[2], a.bc[3], my);
-        double qx[n], qy[n];
-        load_2d<N>(a, (int64_t)row * a.nx + col, mx, my, P.h, P.b, qx, qy);
-#pragma unroll
-        for (int k = 0; k < n; ++k) {
-            P.qa[k] = qy[k];
-            P.qt[k] = qx[k];
-        }
-        side_flux<N, true>(P, a.g);
-    }
     double rmax = 0.0;
-    for (int j = j0; j < j1; ++j) {
-        Side<N, true> C;  // y-frame of the current row
-        double qx[n], qy[n];
-        load_2d<N>(a, (int64_t)j * a.nx + col, mx, false, C.h, C.b, qx, qy);
+    if (wave < nsx * nsy) {  // waves beyond the grid only join the reduction
+        const int sx = wave % nsx;
+        const int sy = wave / nsx;
+        const int c = sx * kOut - 1 + lane;
+        const int j0 = sy * a.rows;
+        const int j1 = min(j0 + a.rows, a.ny);
+        bool mx;
+        const int col = ghost_index(c, a.nx, a.bc[0], a.bc[1], mx);
+        const bool outc = lane >= 1 && lane <= kOut && c < a.nx;
+
+        Cell2<N> A, B;
+        double accA[nf], accB[nf];
+        Raw2<N> nxt;
+        load_row<N>(a, j0 - 1, col, mx, nxt);
+        cell_flux<N>(A, nxt, a.g);  // halo row below the band
 #pragma unroll
-        for (int k = 0; k < n; ++k) {
-            C.qa[k] = qy[k];
-            C.qt[k] = qx[k];
-        }
-        side_flux<N, true>(C, a.g);
-        double Fh[nf], D[nf], accC[nf];
-        face_flux<N, true>(P, C, a.g, a.quad, Fh, D);
-        // frame [h, y.., x..] -> physical [h, x.., y..]
-        if (j > j0) {
-            accP[0] = fma(a.idy, fma(0.5, D[0], Fh[0]), accP[0]);
-#pragma unroll
-            for (int k = 0; k < n; ++k) {
-                accP[1 + n + k] = fma(a.idy, fma(0.5, D[1 + k], Fh[1 + k]), accP[1 + n + k]);
-                accP[1 + k] = fma(a.idy, fma(0.5, D[1 + n + k], Fh[1 + n + k]), accP[1 + k]);
+        for (int f = 0; f < nf; ++f) accA[f] = 0.0;
+        load_row<N>(a, j0, col, mx, nxt);
+        int j = j0;
+        while (true) {
+            Raw2<N> cur = nxt;
+            load_row<N>(a, j + 1, col, mx, nxt);  // next row or the closing halo row
+            row<N>(a, dt, A, accA, B, accB, cur, j, c, outc, j > j0, rmax);
+            if (++j == j1) {
+                close_band<N>(a, dt, B, accB, A, nxt, j1, c, outc, rmax);
+                break;
             }
-            rmax = fmax(rmax, finish_2d<N>(a, dt, (int64_t)(j - 1) * a.nx + c, outc, P.h, P.qt, P.qa, accP));
-        }
-        accC[0] = a.idy * fma(0.5, D[0], -Fh[0]);
-#pragma unroll
-        for (int k = 0; k < n; ++k) {
-            accC[1 + n + k] = a.idy * fma(0.5, D[1 + k], -Fh[1 + k]);
-            accC[1 + k] = a.idy * fma(0.5, D[1 + n + k], -Fh[1 + n + k]);
-        }
-        // x-faces of this row: x-frame qa = qx, qt = qy
-        {
-            Side<N, true> X;
-            X.h = C.h;
-            X.b = C.b;
-#pragma unroll
-            for (int k = 0; k < n; ++k) {
-                X.qa[k] = qx[k];
-                X.qt[k] = qy[k];
-            }
-            side_flux<N, true>(X, a.g);
-            Side<N, true> R;
-            R.h = shfl_dn(X.h);
-            R.b = shfl_dn(X.b);
-            R.Fh = shfl_dn(X.Fh);
-            R.lam = shfl_dn(X.lam);
-#pragma unroll
-            for (int k = 0; k < n; ++k) {
-                R.qa[k] = shfl_dn(X.qa[k]);
-                R.qt[k] = shfl_dn(X.qt[k]);
-                R.Fa[k] = shfl_dn(X.Fa[k]);
-                R.Ft[k] = shfl_dn(X.Ft[k]);
-            }
-            double Gh[nf], E[nf];
-            face_flux<N, true>(X, R, a.g, a.quad, Gh, E);
-#pragma unroll
-            for (int f = 0; f < nf; ++f) {
-                double own = fma(0.5, E[f], Gh[f]);
-                double oth = fma(0.5, E[f], -Gh[f]);
-                accC[f] = fma(a.idx, own + shfl_up1(oth), accC[f]);
+            cur = nxt;
+            load_row<N>(a, j + 1, col, mx, nxt);
+            row<N>(a, dt, B, accB, A, accA, cur, j, c, outc, true, rmax);
+            if (++j == j1) {
+                close_band<N>(a, dt, A, accA, B, nxt, j1, c, outc, rmax);
+                break;
             }
         }
-        P = C;
-#pragma unroll
-        for (int f = 0; f < nf; ++f) accP[f] = accC[f];
-    }
-    // closing y-face of the strip
-    {
-        bool my;
-        const int row = ghost_index(j1, a.ny, a.bc[2], a.bc[3], my);
-        Side<N, true> C;
-        double qx[n], qy[n];
-        load_2d<N>(a, (int64_t)row * a.nx + col, mx, my, C.h, C.b, qx, qy);
-#pragma unroll
-        for (int k = 0; k < n; ++k) {
-            C.qa[k] = qy[k];
-            C.qt[k] = qx[k];
-        }
-        side_flux<N, true>(C, a.g);
-        double Fh[nf], D[nf];
-        face_flux<N, true>(P, C, a.g, a.quad, Fh, D);
-        accP[0] = fma(a.idy, fma(0.5, D[0], Fh[0]), accP[0]);
-#pragma unroll
-        for (int k = 0; k < n; ++k) {
-            accP[1 + n + k] = fma(a.idy, fma(0.5, D[1 + k], Fh[1 + k]), accP[1 + n + k]);
-            accP[1 + k] = fma(a.idy, fma(0.5, D[1 + n + k], Fh[1 + n + k]), accP[1 + k]);
-        }
-        rmax = fmax(rmax, finish_2d<N>(a, dt, (int64_t)(j1 - 1) * a.nx + c, outc, P.h, P.qt, P.qa, accP));
     }
     publish_max(&a.slots[a.sb].rbits, rmax);
 }
@@ -199,6 +307,27 @@ hipError_t launch_step_2d(int level, const StepArgs &a, hipStream_t s)
     SME_LEVEL_SWITCH(level, L2)
 #undef L2
     return hipGetLastError();
+}
+
+int step_2d_vgprs(int level)
+{
+    hipFuncAttributes fa{};
+    hipError_t e = hipErrorInvalidValue;
+#define A2(N) e = hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(&k_step_2d<N>))
+    switch (level) {
+    case 0: A2(0); break;
+    case 1: A2(1); break;
+    case 2: A2(2); break;
+    case 3: A2(3); break;
+    case 4: A2(4); break;
+    case 5: A2(5); break;
+    case 6: A2(6); break;
+    case 7: A2(7); break;
+    case 8: A2(8); break;
+    default: break;
+    }
+#undef A2
+    return e == hipSuccess ? fa.numRegs : -1;
 }
 
 }  // namespace sme

@@ -7,8 +7,8 @@
 // t_k = qt_k / h, the SME flux of Sec. 3.4 (the 2D flux blocks; Eq. (1) in 1D)
 // projected on n reads
 //     F_h     = qa_0
-//     F_a,k   = (1/M_k) sum_ij qa_i a_j A_ijk + delta_k0 g h^2 / 2
-//     F_t,k   = (1/M_k) sum_ij qa_i t_j A_ijk
+//     F_a,k   = (1/M_k) h sum_ij a_i a_j A_ijk + delta_k0 g h^2 / 2
+//     F_t,k   = (1/M_k) h sum_ij a_i t_j A_ijk
 // (A is symmetric, so this equals n_x F_x + n_y F_y rotated into the frame).
 // The non-conservative product of Eq. (1) / Sec. 3.4 contributes, for k >= 1,
 //     (1/M_k) sum_i abar_i sum_{j>=1} B_ijk d(qa_j)     (normal row)
@@ -23,16 +23,111 @@
 // averages abar_i = int_0^1 qa_i(s)/h(s) ds = c0 qa_i^L + c1 d(qa_i) with
 // c0 = sum_g w_g / h(s_g), c1 = sum_g w_g s_g / h(s_g).
 // The left cell receives Fhat + D/2, the right cell -Fhat + D/2.
+//
+// All tensor contractions are unrolled at compile time over the constexpr
+// basis tensors (sfor below), so only their structurally nonzero entries
+// generate instructions.
 #pragma once
 
 #include <hip/hip_runtime.h>
 #include <math.h>
+
+#include <type_traits>
 
 #include "sme_basis.h"
 
 namespace sme {
 
 constexpr int kMaxQuad = 8;
+
+// compile-time loop: f(integral_constant<int, I>) for I = B .. E-1
+template <int B, int E, typename F>
+__device__ __forceinline__ void sfor(F &&f)
+{
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        sfor<B + 1, E>(f);
+    }
+}
+
+// first j in [j0, n) with A[i][j][k] != 0 (or -1)
+template <int N>
+constexpr int first_nz_A(int i, int k, int j0 = 0)
+{
+    for (int j = j0; j <= N; ++j)
+        if (Basis<N>::T.A[i][j][k] != 0.0) return j;
+    return -1;
+}
+template <int N>
+constexpr int first_nz_B(int i, int k)
+{
+    for (int j = 1; j <= N; ++j)
+        if (Basis<N>::T.B[i][j][k] != 0.0) return j;
+    return -1;
+}
+template <int N>
+constexpr int first_nz_K(int k)
+{
+    for (int j = 0; j <= N; ++j)
+        if (Basis<N>::T.K[j][k] != 0.0) return j;
+    return -1;
+}
+
+// sum_j A[i][j][k] v[j] over the nonzero entries (0 if none)
+template <int N, int I, int K>
+__device__ __forceinline__ double contract_A(const double *v)
+{
+    constexpr int j0 = first_nz_A<N>(I, K);
+    if constexpr (j0 < 0) {
+        return 0.0;
+    } else {
+        double s = Basis<N>::T.A[I][j0][K] * v[j0];
+        sfor<j0 + 1, N + 1>([&](auto J) {
+            constexpr int j = decltype(J)::value;
+            constexpr double c = Basis<N>::T.A[I][j][K];
+            if constexpr (c != 0.0) s = fma(c, v[j], s);
+        });
+        return s;
+    }
+}
+
+// sum_{j>=1} B[i][j][k] v[j]
+template <int N, int I, int K>
+__device__ __forceinline__ double contract_B(const double *v)
+{
+    constexpr int j0 = first_nz_B<N>(I, K);
+    if constexpr (j0 < 0) {
+        return 0.0;
+    } else {
+        double s = Basis<N>::T.B[I][j0][K] * v[j0];
+        sfor<j0 + 1, N + 1>([&](auto J) {
+            constexpr int j = decltype(J)::value;
+            constexpr double c = Basis<N>::T.B[I][j][K];
+            if constexpr (c != 0.0) s = fma(c, v[j], s);
+        });
+        return s;
+    }
+}
+
+// qf_k = sum_ij u_i v_j A_ijk (the quadratic forms of the flux), k = 0..N
+template <int N>
+__device__ __forceinline__ void quad_form(const double *u, const double *v, double *out)
+{
+    sfor<0, N + 1>([&](auto K) {
+        constexpr int k = decltype(K)::value;
+        double acc = 0.0;
+        bool first = true;
+        sfor<0, N + 1>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            if constexpr (first_nz_A<N>(i, k) >= 0) {
+                double c = contract_A<N, i, k>(v);
+                acc = first ? u[i] * c : fma(u[i], c, acc);
+                first = false;
+            }
+        });
+        out[k] = acc;
+    });
+}
 
 // 1/x for the positive depths of the scheme: hardware estimate refined by two
 // Newton steps (error below one ulp after the second step).
@@ -45,6 +140,22 @@ __device__ __forceinline__ double rcp(double x)
     return fma(r, e, r);
 }
 
+// sqrt(x) for x > 0 by Goldschmidt's iteration from the hardware reciprocal
+// square-root estimate (about 26 correct bits): one coupled iteration doubles
+// the bits, a final residual correction rounds to within an ulp.  Negative
+// or NaN input gives NaN (the estimate does).
+__device__ __forceinline__ double sqrt_pos(double x)
+{
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y;
+    double h = 0.5 * y;
+    const double r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    const double d = fma(-g, g, x);
+    return fma(d, h, g);
+}
+
 // Wave-speed bound lam = |a_0| + sqrt(g h + (sum_{j>=1} |a_j|)^2)
 template <int N>
 __device__ __forceinline__ double lam_bound(double gh, const double *a)
@@ -52,17 +163,16 @@ __device__ __forceinline__ double lam_bound(double gh, const double *a)
     double s = 0.0;
 #pragma unroll
     for (int j = 1; j <= N; ++j) s += fabs(a[j]);
-    return fabs(a[0]) + sqrt(fma(s, s, gh));
+    return fabs(a[0]) + sqrt_pos(fma(s, s, gh));
 }
 
-// One side of a face in the face frame.
+// One side of a face in the face frame (F_h = qa_0 is not stored).
 template <int N, bool TAN>
 struct Side {
     static constexpr int n = N + 1;
     double h, b;
     double qa[n];
     double qt[TAN ? n : 1];
-    double Fh;
     double Fa[n];
     double Ft[TAN ? n : 1];
     double lam;
@@ -73,99 +183,106 @@ template <int N, bool TAN>
 __device__ __forceinline__ void side_flux(Side<N, TAN> &s, double g)
 {
     constexpr int n = N + 1;
-    const auto &T = Basis<N>::T;
-    double ih = rcp(s.h);
+    const double ih = rcp(s.h);
     double a[n], t[TAN ? n : 1];
 #pragma unroll
     for (int k = 0; k < n; ++k) a[k] = s.qa[k] * ih;
+    double qf[n];
+    quad_form<N>(s.qa, a, qf);
+#pragma unroll
+    for (int k = 0; k < n; ++k) s.Fa[k] = qf[k] * Basis<N>::T.invM[k];
     if constexpr (TAN) {
 #pragma unroll
         for (int k = 0; k < n; ++k) t[k] = s.qt[k] * ih;
-    }
-    s.Fh = s.qa[0];
+        double qt[n];
+        quad_form<N>(s.qa, t, qt);
 #pragma unroll
-    for (int k = 0; k < n; ++k) {
-        double fa = 0.0, ft = 0.0;
-#pragma unroll
-        for (int i = 0; i < n; ++i) {
-            double sa = 0.0, st = 0.0;
-#pragma unroll
-            for (int j = 0; j < n; ++j) {
-                if (T.A[i][j][k] != 0.0) {
-                    sa = fma(T.A[i][j][k], a[j], sa);
-                    if constexpr (TAN) st = fma(T.A[i][j][k], t[j], st);
-                }
-            }
-            fa = fma(s.qa[i], sa, fa);
-            if constexpr (TAN) ft = fma(s.qa[i], st, ft);
-        }
-        s.Fa[k] = fa * T.invM[k];
-        if constexpr (TAN) s.Ft[k] = ft * T.invM[k];
+        for (int k = 0; k < n; ++k) s.Ft[k] = qt[k] * Basis<N>::T.invM[k];
     }
     s.Fa[0] = fma(0.5 * g * s.h, s.h, s.Fa[0]);
     s.lam = lam_bound<N>(g * s.h, a);
 }
 
+// Gauss-Legendre points on [0, 1]: the 3-point rule in scalars (no indexing),
+// any other rule through a device pointer read with uniform loads.
 struct Quad {
     int n;
-    double s[kMaxQuad];
-    double w[kMaxQuad];
+    double s0, s1, s2, w0, w1, w2;
+    const double *s;
+    const double *w;
 };
 
-// Face fluxes: Fhat (Rusanov) and D (path-integrated NC fluctuation), frame fields.
-// Output layout: [h, a_0..a_N, t_0..t_N].
+// c0 = sum_g w_g / h(s_g), c1 = sum_g w_g s_g / h(s_g),  h(s) = hL + s dh
+__device__ __forceinline__ void path_weights(const Quad &q, double hL, double dh, double &c0, double &c1)
+{
+    if (q.n == 3) {
+        const double r0 = q.w0 * rcp(fma(q.s0, dh, hL));
+        const double r1 = q.w1 * rcp(fma(q.s1, dh, hL));
+        const double r2 = q.w2 * rcp(fma(q.s2, dh, hL));
+        c0 = r0 + r1 + r2;
+        c1 = fma(r0, q.s0, fma(r1, q.s1, r2 * q.s2));
+    } else {
+        c0 = 0.0;
+        c1 = 0.0;
+        for (int g = 0; g < q.n; ++g) {
+            const double sg = q.s[g];
+            const double r = q.w[g] * rcp(fma(sg, dh, hL));
+            c0 += r;
+            c1 = fma(r, sg, c1);
+        }
+    }
+}
+
+// Face fluxes: Fhat (Rusanov) and D (path-integrated NC fluctuation), frame
+// fields [h, a_0..a_N, t_0..t_N].
 template <int N, bool TAN>
 __device__ __forceinline__ void face_flux(const Side<N, TAN> &L, const Side<N, TAN> &R, double g,
                                           const Quad &q, double *Fhat, double *D)
 {
     constexpr int n = N + 1;
-    const auto &T = Basis<N>::T;
-    const double s = fmax(L.lam, R.lam);
-    const double hs = 0.5 * s;
+    const double hs = 0.5 * fmax(L.lam, R.lam);
     // Rusanov on W = (h + b, qa, qt)
-    Fhat[0] = 0.5 * (L.Fh + R.Fh) - hs * ((R.h + R.b) - (L.h + L.b));
-#pragma unroll
-    for (int k = 0; k < n; ++k) Fhat[1 + k] = 0.5 * (L.Fa[k] + R.Fa[k]) - hs * (R.qa[k] - L.qa[k]);
-    if constexpr (TAN) {
-#pragma unroll
-        for (int k = 0; k < n; ++k)
-            Fhat[1 + n + k] = 0.5 * (L.Ft[k] + R.Ft[k]) - hs * (R.qt[k] - L.qt[k]);
-    }
-    // path averages of the velocities
-    const double dh = R.h - L.h;
-    double c0 = 0.0, c1 = 0.0;
-    for (int gq = 0; gq < q.n; ++gq) {
-        double r = rcp(fma(q.s[gq], dh, L.h));
-        double wr = q.w[gq] * r;
-        c0 += wr;
-        c1 = fma(wr, q.s[gq], c1);
-    }
+    Fhat[0] = fma(0.5, L.qa[0] + R.qa[0], -hs * ((R.h + R.b) - (L.h + L.b)));
     double dqa[n];
 #pragma unroll
-    for (int k = 0; k < n; ++k) dqa[k] = R.qa[k] - L.qa[k];
-    // W_ik = sum_{j>=1} B_ijk d(qa_j)
-    D[0] = 0.0;
-    D[1] = g * 0.5 * (L.h + R.h) * (R.b - L.b);
-#pragma unroll
-    for (int k = 1; k < n; ++k) {
-        double va = 0.0, vt = 0.0;
-#pragma unroll
-        for (int i = 0; i < n; ++i) {
-            double w = 0.0;
-#pragma unroll
-            for (int j = 1; j < n; ++j)
-                if (T.B[i][j][k] != 0.0) w = fma(T.B[i][j][k], dqa[j], w);
-            double abar = fma(c0, L.qa[i], c1 * dqa[i]);
-            va = fma(abar, w, va);
-            if constexpr (TAN) {
-                double tbar = fma(c0, L.qt[i], c1 * (R.qt[i] - L.qt[i]));
-                vt = fma(tbar, w, vt);
-            }
-        }
-        D[1 + k] = va * T.invM[k];
-        if constexpr (TAN) D[1 + n + k] = vt * T.invM[k];
+    for (int k = 0; k < n; ++k) {
+        dqa[k] = R.qa[k] - L.qa[k];
+        Fhat[1 + k] = fma(0.5, L.Fa[k] + R.Fa[k], -hs * dqa[k]);
     }
+    double dqt[TAN ? n : 1];
+    if constexpr (TAN) {
+#pragma unroll
+        for (int k = 0; k < n; ++k) {
+            dqt[k] = R.qt[k] - L.qt[k];
+            Fhat[1 + n + k] = fma(0.5, L.Ft[k] + R.Ft[k], -hs * dqt[k]);
+        }
+    }
+    // path averages of the velocities
+    double c0, c1;
+    path_weights(q, L.h, R.h - L.h, c0, c1);
+    D[0] = 0.0;
+    D[1] = g * (0.5 * (L.h + R.h)) * (R.b - L.b);
     if constexpr (TAN) D[1 + n] = 0.0;
+    sfor<1, n>([&](auto K) {
+        constexpr int k = decltype(K)::value;
+        double va = 0.0, vt = 0.0;
+        bool first = true;
+        sfor<0, n>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            if constexpr (first_nz_B<N>(i, k) >= 0) {
+                const double w = contract_B<N, i, k>(dqa);
+                const double abar = fma(c0, L.qa[i], c1 * dqa[i]);
+                va = first ? abar * w : fma(abar, w, va);
+                if constexpr (TAN) {
+                    const double tbar = fma(c0, L.qt[i], c1 * dqt[i]);
+                    vt = first ? tbar * w : fma(tbar, w, vt);
+                }
+                first = false;
+            }
+        });
+        D[1 + k] = va * Basis<N>::T.invM[k];
+        if constexpr (TAN) D[1 + n + k] = vt * Basis<N>::T.invM[k];
+    });
 }
 
 // Friction source (Sec. 3.4: slip at the bed, Newtonian bulk), explicit Euler
@@ -176,7 +293,6 @@ template <int N>
 __device__ __forceinline__ void friction(double *q, double ih, double dt, double c_slip, double nu)
 {
     constexpr int n = N + 1;
-    const auto &T = Basis<N>::T;
     double al[n];
     double ub = 0.0;
 #pragma unroll
@@ -186,15 +302,21 @@ __device__ __forceinline__ void friction(double *q, double ih, double dt, double
     }
     const double cub = c_slip * ub;
     const double nuh = nu * ih;
-#pragma unroll
-    for (int k = 0; k < n; ++k) {
+    sfor<0, n>([&](auto K) {
+        constexpr int k = decltype(K)::value;
         double bulk = 0.0;
-#pragma unroll
-        for (int j = 0; j < n; ++j)
-            if (T.K[j][k] != 0.0) bulk = fma(T.K[j][k], al[j], bulk);
-        double S = -(cub + nuh * bulk) * T.invM[k];
+        constexpr int j0 = first_nz_K<N>(k);
+        if constexpr (j0 >= 0) {
+            bulk = Basis<N>::T.K[j0][k] * al[j0];
+            sfor<j0 + 1, n>([&](auto J) {
+                constexpr int j = decltype(J)::value;
+                constexpr double c = Basis<N>::T.K[j][k];
+                if constexpr (c != 0.0) bulk = fma(c, al[j], bulk);
+            });
+        }
+        const double S = -fma(nuh, bulk, cub) * Basis<N>::T.invM[k];
         q[k] = fma(dt, S, q[k]);
-    }
+    });
 }
 
 }  // namespace sme

@@ -58,6 +58,7 @@ struct StepArgs {
 // host-side launchers (defined in sme_kernels.hip); level is 0..8
 hipError_t launch_step_1d(int level, const StepArgs &a, hipStream_t s);
 hipError_t launch_step_2d(int level, const StepArgs &a, hipStream_t s);
+int step_2d_vgprs(int level);  // registers per lane of the structured step kernel, -1 on error
 hipError_t launch_step_tri(int level, const StepArgs &a, hipStream_t s);
 hipError_t launch_eig(int dim, int kind, int level, const StepArgs &a, hipStream_t s);
 hipError_t launch_slots_reset(Slot *slots, ErrWord *err, int sa, hipStream_t s);

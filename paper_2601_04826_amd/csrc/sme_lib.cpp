@@ -56,6 +56,7 @@ struct sme_ctx {
     int64_t *to_caller = nullptr;    // internal cell -> caller cell
     Slot *slots = nullptr;
     ErrWord *err = nullptr;
+    double *quad_dev = nullptr;      // Gauss points [kMaxQuad] then weights [kMaxQuad]
     int cur = 0;   // which q[] holds the state
     int sa = 0;    // slot describing the current state
     bool has_state = false;
@@ -286,6 +287,35 @@ std::vector<int64_t> rcm_order(const std::vector<int32_t> &nbr, int64_t n)
     return order;
 }
 
+// Height of the row band each wave of the structured kernel marches up.
+// Every band costs its rows plus about 1.5 rows of halo work, and waves run in
+// generations of (compute units x 4 SIMDs x waves per SIMD); a short last
+// generation costs a full band time.  Pick the height that minimises
+// generations x (rows + 1.5) for this grid, level and device.
+int pick_rows(int level, int64_t nx, int64_t ny)
+{
+    int dev = 0, cus = 256;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+        cus = std::max(1, prop.multiProcessorCount);
+    const int regs = step_2d_vgprs(level);
+    const int per_simd = regs > 0 ? std::max(1, std::min(8, 512 / ((regs + 7) / 8 * 8))) : 2;
+    const int64_t slots = (int64_t)cus * 4 * per_simd;
+    const int64_t nsx = (nx + 61) / 62;
+    int best = 8;
+    double best_cost = 1e300;
+    for (int rows = 2; rows <= 64; ++rows) {
+        const int64_t waves = nsx * ((ny + rows - 1) / rows);
+        const int64_t gens = (waves + slots - 1) / slots;
+        const double cost = (double)gens * (rows + 1.5);
+        if (cost < best_cost - 1e-9) {
+            best_cost = cost;
+            best = rows;
+        }
+    }
+    return best;
+}
+
 template <typename T>
 int dalloc(sme_ctx *c, T **p, size_t count)
 {
@@ -382,6 +412,13 @@ int get_graph(sme_ctx *c, double t_end, hipGraphExec_t *out)
     return SME_OK;
 }
 
+int nonphys(sme_ctx *c, const ErrWord &e)
+{
+    if (e.first_step == 0) return fail(c, SME_ENONPHYS, "the loaded state is non-physical (h <= 0 or non-finite)");
+    return fail(c, SME_ENONPHYS, "non-physical state (h <= 0 or non-finite) produced by step %llu",
+                (unsigned long long)e.first_step);
+}
+
 int read_slot(sme_ctx *c, Slot *s, ErrWord *e)
 {
     HIPCHK(c, hipMemcpyAsync(s, c->slots + c->sa, sizeof(Slot), hipMemcpyDeviceToHost, c->stream));
@@ -441,8 +478,15 @@ int sme_init(sme_ctx **out, int level, const sme_mesh *mesh, const sme_params *p
     c->ncells = nc;
     c->stride = (nc + 255) / 256 * 256;
     c->p = *params;
+    double qs[kMaxQuad] = {0}, qw[kMaxQuad] = {0};
+    gauss_legendre01(params->quad_points, qs, qw);
     c->quad.n = params->quad_points;
-    gauss_legendre01(params->quad_points, c->quad.s, c->quad.w);
+    c->quad.s0 = qs[0];
+    c->quad.s1 = qs[1];
+    c->quad.s2 = qs[2];
+    c->quad.w0 = qw[0];
+    c->quad.w1 = qw[1];
+    c->quad.w2 = qw[2];
     for (int s = 0; s < 4; ++s) c->bc[s] = mesh->bc[s];
     if (hipGetDevice(&c->device) != hipSuccess) {
         delete c;
@@ -467,7 +511,7 @@ int sme_init(sme_ctx **out, int level, const sme_mesh *mesh, const sme_params *p
         c->dx = (mesh->x1 - mesh->x0) / mesh->nx;
         c->dy = (mesh->y1 - mesh->y0) / mesh->ny;
         const char *env = getenv("SME_ROWS");
-        c->rows = env ? std::max(1, atoi(env)) : 16;
+        c->rows = env ? std::max(1, atoi(env)) : pick_rows(c->level, c->nx, c->ny);
     }
     int rc = SME_OK;
     rc = rc ? rc : dalloc(c, &c->q[0], (size_t)nf * c->stride);
@@ -475,6 +519,16 @@ int sme_init(sme_ctx **out, int level, const sme_mesh *mesh, const sme_params *p
     rc = rc ? rc : dalloc(c, &c->b, (size_t)c->stride);
     rc = rc ? rc : dalloc(c, &c->slots, 3);
     rc = rc ? rc : dalloc(c, &c->err, 1);
+    rc = rc ? rc : dalloc(c, &c->quad_dev, 2 * kMaxQuad);
+    if (!rc) {
+        double buf[2 * kMaxQuad];
+        memcpy(buf, qs, sizeof qs);
+        memcpy(buf + kMaxQuad, qw, sizeof qw);
+        if (hipMemcpy(c->quad_dev, buf, sizeof buf, hipMemcpyHostToDevice) != hipSuccess)
+            rc = fail(c, SME_EHIP, "quadrature upload failed");
+        c->quad.s = c->quad_dev;
+        c->quad.w = c->quad_dev + kMaxQuad;
+    }
     std::vector<int64_t> order;  // internal position -> caller cell
     if (!rc && mesh->kind == SME_MESH_2D_TRI) {
         TriGeom g;
@@ -634,9 +688,7 @@ int sme_run(sme_ctx *c, int64_t n_steps, double t_end, double *t_out, int64_t *s
         if (r) return r;
         if (t_out) *t_out = s.t;
         if (steps_done) *steps_done = s.step;
-        if (e.flag)
-            return fail(c, SME_ENONPHYS, "non-physical state (h <= 0 or non-finite) produced by step %llu",
-                        (unsigned long long)e.first_step);
+        if (e.flag) return nonphys(c, e);
     }
     return SME_OK;
 }
@@ -650,9 +702,7 @@ int sme_time(sme_ctx *c, double *t, int64_t *steps)
     if (r) return r;
     if (t) *t = s.t;
     if (steps) *steps = s.step;
-    if (e.flag)
-        return fail(c, SME_ENONPHYS, "non-physical state (h <= 0 or non-finite) produced by step %llu",
-                    (unsigned long long)e.first_step);
+    if (e.flag) return nonphys(c, e);
     return SME_OK;
 }
 
@@ -709,6 +759,7 @@ void sme_destroy(sme_ctx *c)
     (void)hipFree(c->to_caller);
     (void)hipFree(c->slots);
     (void)hipFree(c->err);
+    (void)hipFree(c->quad_dev);
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }

@@ -66,19 +66,34 @@ __device__ __forceinline__ double wave_max(double v)
     return v;
 }
 
+// Block-wide maximum of a non-negative double, published with one unsigned
+// 64-bit atomic max per block.  Every thread of the block must call it.
 __device__ __forceinline__ void publish_max(unsigned long long *dst, double v)
 {
+    __shared__ double part[kBlock / kWave];
     v = wave_max(v);
-    if ((threadIdx.x & (kWave - 1)) == 0 && v > 0.0)
-        atomicMax(dst, (unsigned long long)__double_as_longlong(v));
+    if ((threadIdx.x & (kWave - 1)) == 0) part[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = part[0];
+#pragma unroll
+        for (int w = 1; w < kBlock / kWave; ++w) m = fmax(m, part[w]);
+        if (m > 0.0) atomicMax(dst, (unsigned long long)__double_as_longlong(m));
+    }
+}
+
+// record a non-physical value (h <= 0 or non-finite) produced by step `step`
+__device__ __forceinline__ void flag_bad_at(const StepArgs &a, bool bad, long long step)
+{
+    if (bad) {
+        atomicOr(&a.err->flag, 1u);
+        atomicMin(&a.err->first_step, (unsigned long long)step);
+    }
 }
 
 __device__ __forceinline__ void flag_bad(const StepArgs &a, bool bad)
 {
-    if (bad) {
-        atomicOr(&a.err->flag, 1u);
-        atomicMin(&a.err->first_step, (unsigned long long)(a.slots[a.sa].step + 1));
-    }
+    flag_bad_at(a, bad, a.slots[a.sa].step + 1);
 }
 
 template <int N>
@@ -131,10 +146,21 @@ __device__ __forceinline__ double cfl_ratio_tri(double g, double h, double ih, c
     return r;
 }
 
-template <typename T>
-__device__ __forceinline__ T shfl_dn(T v) { return __shfl_down(v, 1, kWave); }
-template <typename T>
-__device__ __forceinline__ T shfl_up1(T v) { return __shfl_up(v, 1, kWave); }
+// Cross-lane moves by one lane with DPP wave shifts (GFX9 wave_shl:1 /
+// wave_shr:1): shfl_dn gives lane i the value of lane i + 1, shfl_up1 the
+// value of lane i - 1; the lane without a source keeps its own value.
+__device__ __forceinline__ double shfl_dn(double v)
+{
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    return __hiloint2double(__builtin_amdgcn_update_dpp(hi, hi, 0x130, 0xf, 0xf, false),
+                            __builtin_amdgcn_update_dpp(lo, lo, 0x130, 0xf, 0xf, false));
+}
+__device__ __forceinline__ double shfl_up1(double v)
+{
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    return __hiloint2double(__builtin_amdgcn_update_dpp(hi, hi, 0x138, 0xf, 0xf, false),
+                            __builtin_amdgcn_update_dpp(lo, lo, 0x138, 0xf, 0xf, false));
+}
 
 // Source column / row for a (possibly ghost) index along one axis.
 // Returns the index to load and whether the normal momenta are mirrored.
