@@ -19,7 +19,10 @@ SOURCES = ["k_step_1d.hip", "k_step_2d.hip", "k_step_tri.hip", "k_misc.hip", "sm
 FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
          # no packed FP32 instructions anywhere in the device code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-         "-Wno-pass-failed"]
+         "-Wno-pass-failed", "-fconstexpr-steps=100000000",
+         # keep constant materialisation next to its use: hoisting hundreds of
+         # FP64 tensor literals out of the row loop only spills them
+         "-mllvm", "-disable-machine-licm"]
 
 
 def _compile(src):

@@ -10,7 +10,8 @@
 //   * the y-face between the previous and the current row is computed once,
 //     with the previous row held in registers (two register sets that swap
 //     roles every row, so nothing is copied);
-//   * the next row's loads are issued before the current row is computed.
+//   * rows are loaded one at a time (registers go to occupancy, three waves per
+//     SIMD at level 2, rather than to a prefetched row).
 #include <hip/hip_runtime.h>
 
 #include "sme_step_common.h"
@@ -80,16 +81,9 @@ __device__ __forceinline__ void cell_flux(Cell2<N> &c, const Raw2<N> &r, double 
         al[k] = c.qx[k] * ih;
         be[k] = c.qy[k] * ih;
     }
-    double fxx[n], fyy[n], ft[n];
-    quad_form<N>(c.qx, al, fxx);
-    quad_form<N>(c.qy, be, fyy);
-    quad_form<N>(c.qx, be, ft);
-#pragma unroll
-    for (int k = 0; k < n; ++k) {
-        c.Fxx[k] = fxx[k] * Basis<N>::T.invM[k];
-        c.Fyy[k] = fyy[k] * Basis<N>::T.invM[k];
-        c.Ft[k] = ft[k] * Basis<N>::T.invM[k];
-    }
+    quad_form<N>(c.qx, al, c.Fxx);
+    quad_form<N>(c.qy, be, c.Fyy);
+    quad_form<N>(c.qx, be, c.Ft);
     const double gh = g * c.h;
     const double p = 0.5 * gh * c.h;
     c.Fxx[0] += p;
@@ -278,15 +272,15 @@ __global__ __launch_bounds__(kBlock) void k_step_2d(StepArgs a)
         int j = j0;
         while (true) {
             Raw2<N> cur = nxt;
-            load_row<N>(a, j + 1, col, mx, nxt);  // next row or the closing halo row
             row<N>(a, dt, A, accA, B, accB, cur, j, c, outc, j > j0, rmax);
+            load_row<N>(a, j + 1, col, mx, nxt);
             if (++j == j1) {
                 close_band<N>(a, dt, B, accB, A, nxt, j1, c, outc, rmax);
                 break;
             }
             cur = nxt;
-            load_row<N>(a, j + 1, col, mx, nxt);
             row<N>(a, dt, B, accB, A, accA, cur, j, c, outc, true, rmax);
+            load_row<N>(a, j + 1, col, mx, nxt);
             if (++j == j1) {
                 close_band<N>(a, dt, A, accA, B, nxt, j1, c, outc, rmax);
                 break;

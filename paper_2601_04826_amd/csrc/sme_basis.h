@@ -93,14 +93,30 @@ constexpr IPoly phi_int_scaled(int j)
     return r;
 }
 
-// exact int_0^1 p / scale, rounded once to double
-constexpr double integrate(const IPoly &p, __int128 scale)
+struct Rat {
+    __int128 num, den;
+};
+
+// exact int_0^1 p / scale as a reduced fraction
+constexpr Rat integrate(const IPoly &p, __int128 scale)
 {
     __int128 den = 1;  // lcm(1..deg+1)
     for (int m = 1; m <= p.deg + 1; ++m) den = den / gcd128(den, m) * m;
     __int128 num = 0;
     for (int m = 0; m <= p.deg; ++m) num += p.c[m] * (den / (m + 1));
     den *= scale;
+    __int128 g = gcd128(num, den);
+    if (g != 0) {
+        num /= g;
+        den /= g;
+    }
+    return Rat{num, den};
+}
+
+// mul * r rounded once to double
+constexpr double to_double(Rat r, __int128 mul = 1)
+{
+    __int128 num = r.num * mul, den = r.den;
     __int128 g = gcd128(num, den);
     if (g != 0) {
         num /= g;
@@ -117,6 +133,11 @@ struct Tensors {
     double A[n][n][n];
     double B[n][n][n];
     double K[n][n];
+    // the same tensors divided by M_k (their last index), each rounded once:
+    // AM_ijk = A_ijk / M_k, BM_ijk = B_ijk / M_k, KM_jk = K_jk / M_k
+    double AM[n][n][n];
+    double BM[n][n][n];
+    double KM[n][n];
 };
 
 template <int N>
@@ -131,7 +152,7 @@ constexpr Tensors<N> make_tensors()
         Ph[k] = phi_int_scaled(k);
     }
     for (int k = 0; k < n; ++k) {
-        t.M[k] = integrate(pmul(ph[k], ph[k]), 1);
+        t.M[k] = to_double(integrate(pmul(ph[k], ph[k]), 1));
         t.invM[k] = (double)(2 * k + 1);  // exact: M_k = 1 / (2k + 1)
     }
     for (int i = 0; i < n; ++i)
@@ -139,12 +160,20 @@ constexpr Tensors<N> make_tensors()
             IPoly pij = pmul(ph[i], ph[j]);
             IPoly qij = pmul(ph[i], Ph[j]);
             for (int k = 0; k < n; ++k) {
-                t.A[i][j][k] = integrate(pmul(pij, ph[k]), 1);
-                t.B[i][j][k] = integrate(pmul(qij, dph[k]), kPhiScale);
+                const Rat a = integrate(pmul(pij, ph[k]), 1);
+                const Rat b = integrate(pmul(qij, dph[k]), kPhiScale);
+                t.A[i][j][k] = to_double(a);
+                t.B[i][j][k] = to_double(b);
+                t.AM[i][j][k] = to_double(a, 2 * k + 1);  // 1 / M_k = 2k + 1 exactly
+                t.BM[i][j][k] = to_double(b, 2 * k + 1);
             }
         }
     for (int j = 0; j < n; ++j)
-        for (int k = 0; k < n; ++k) t.K[j][k] = integrate(pmul(dph[j], dph[k]), 1);
+        for (int k = 0; k < n; ++k) {
+            const Rat kk = integrate(pmul(dph[j], dph[k]), 1);
+            t.K[j][k] = to_double(kk);
+            t.KM[j][k] = to_double(kk, 2 * k + 1);
+        }
     return t;
 }
 

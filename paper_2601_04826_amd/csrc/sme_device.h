@@ -55,25 +55,25 @@ template <int N>
 constexpr int first_nz_A(int i, int k, int j0 = 0)
 {
     for (int j = j0; j <= N; ++j)
-        if (Basis<N>::T.A[i][j][k] != 0.0) return j;
+        if (Basis<N>::T.AM[i][j][k] != 0.0) return j;
     return -1;
 }
 template <int N>
 constexpr int first_nz_B(int i, int k)
 {
     for (int j = 1; j <= N; ++j)
-        if (Basis<N>::T.B[i][j][k] != 0.0) return j;
+        if (Basis<N>::T.BM[i][j][k] != 0.0) return j;
     return -1;
 }
 template <int N>
 constexpr int first_nz_K(int k)
 {
     for (int j = 0; j <= N; ++j)
-        if (Basis<N>::T.K[j][k] != 0.0) return j;
+        if (Basis<N>::T.KM[j][k] != 0.0) return j;
     return -1;
 }
 
-// sum_j A[i][j][k] v[j] over the nonzero entries (0 if none)
+// sum_j A[i][j][k] v[j] / M_k over the nonzero entries (0 if none)
 template <int N, int I, int K>
 __device__ __forceinline__ double contract_A(const double *v)
 {
@@ -81,17 +81,17 @@ __device__ __forceinline__ double contract_A(const double *v)
     if constexpr (j0 < 0) {
         return 0.0;
     } else {
-        double s = Basis<N>::T.A[I][j0][K] * v[j0];
+        double s = Basis<N>::T.AM[I][j0][K] * v[j0];
         sfor<j0 + 1, N + 1>([&](auto J) {
             constexpr int j = decltype(J)::value;
-            constexpr double c = Basis<N>::T.A[I][j][K];
+            constexpr double c = Basis<N>::T.AM[I][j][K];
             if constexpr (c != 0.0) s = fma(c, v[j], s);
         });
         return s;
     }
 }
 
-// sum_{j>=1} B[i][j][k] v[j]
+// sum_{j>=1} B[i][j][k] v[j] / M_k
 template <int N, int I, int K>
 __device__ __forceinline__ double contract_B(const double *v)
 {
@@ -99,17 +99,17 @@ __device__ __forceinline__ double contract_B(const double *v)
     if constexpr (j0 < 0) {
         return 0.0;
     } else {
-        double s = Basis<N>::T.B[I][j0][K] * v[j0];
+        double s = Basis<N>::T.BM[I][j0][K] * v[j0];
         sfor<j0 + 1, N + 1>([&](auto J) {
             constexpr int j = decltype(J)::value;
-            constexpr double c = Basis<N>::T.B[I][j][K];
+            constexpr double c = Basis<N>::T.BM[I][j][K];
             if constexpr (c != 0.0) s = fma(c, v[j], s);
         });
         return s;
     }
 }
 
-// qf_k = sum_ij u_i v_j A_ijk (the quadratic forms of the flux), k = 0..N
+// qf_k = (1/M_k) sum_ij u_i v_j A_ijk (the quadratic forms of the flux), k = 0..N
 template <int N>
 __device__ __forceinline__ void quad_form(const double *u, const double *v, double *out)
 {
@@ -187,17 +187,11 @@ __device__ __forceinline__ void side_flux(Side<N, TAN> &s, double g)
     double a[n], t[TAN ? n : 1];
 #pragma unroll
     for (int k = 0; k < n; ++k) a[k] = s.qa[k] * ih;
-    double qf[n];
-    quad_form<N>(s.qa, a, qf);
-#pragma unroll
-    for (int k = 0; k < n; ++k) s.Fa[k] = qf[k] * Basis<N>::T.invM[k];
+    quad_form<N>(s.qa, a, s.Fa);
     if constexpr (TAN) {
 #pragma unroll
         for (int k = 0; k < n; ++k) t[k] = s.qt[k] * ih;
-        double qt[n];
-        quad_form<N>(s.qa, t, qt);
-#pragma unroll
-        for (int k = 0; k < n; ++k) s.Ft[k] = qt[k] * Basis<N>::T.invM[k];
+        quad_form<N>(s.qa, t, s.Ft);
     }
     s.Fa[0] = fma(0.5 * g * s.h, s.h, s.Fa[0]);
     s.lam = lam_bound<N>(g * s.h, a);
@@ -280,8 +274,8 @@ __device__ __forceinline__ void face_flux(const Side<N, TAN> &L, const Side<N, T
                 first = false;
             }
         });
-        D[1 + k] = va * Basis<N>::T.invM[k];
-        if constexpr (TAN) D[1 + n + k] = vt * Basis<N>::T.invM[k];
+        D[1 + k] = va;
+        if constexpr (TAN) D[1 + n + k] = vt;
     });
 }
 
@@ -307,14 +301,15 @@ __device__ __forceinline__ void friction(double *q, double ih, double dt, double
         double bulk = 0.0;
         constexpr int j0 = first_nz_K<N>(k);
         if constexpr (j0 >= 0) {
-            bulk = Basis<N>::T.K[j0][k] * al[j0];
+            bulk = Basis<N>::T.KM[j0][k] * al[j0];
             sfor<j0 + 1, n>([&](auto J) {
                 constexpr int j = decltype(J)::value;
-                constexpr double c = Basis<N>::T.K[j][k];
+                constexpr double c = Basis<N>::T.KM[j][k];
                 if constexpr (c != 0.0) bulk = fma(c, al[j], bulk);
             });
         }
-        const double S = -fma(nuh, bulk, cub) * Basis<N>::T.invM[k];
+        // S_k = -(C u_b / M_k + (nu/h) sum_j K_jk alpha_j / M_k)
+        const double S = -fma(nuh, bulk, cub * Basis<N>::T.invM[k]);
         q[k] = fma(dt, S, q[k]);
     });
 }
