@@ -143,6 +143,16 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
     ms = ev0.elapsed_time(ev1)
+    # average duration of one step-kernel launch: HIP events recorded on the
+    # library's stream right before and after single-step launches
+    launches = max(10, min(args.steps, 50))
+    pairs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(launches)]
+    for e0, e1 in pairs:
+        e0.record(stream)
+        solver.step(0.0)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    per_launch_ms = sorted(e0.elapsed_time(e1) for e0, e1 in pairs)[launches // 2]
     t_sim, nsteps = solver.time()
     solver.close()
     print(f"[bench] {args.steps} steps in {ms:.3f} ms (events), {wall * 1e3:.3f} ms wall; "
@@ -150,7 +160,7 @@ def main():
 
     ncells = problem["ncells"]
     value = ncells * args.steps / (ms * 1e-3)
-    per_launch_s = ms * 1e-3 / args.steps  # one step kernel per step
+    per_launch_s = ms * 1e-3 / args.steps  # one step kernel per step of the timed region
     alg_bytes = bytes_per_cell(problem["kind"], problem["level"]) * ncells
     achieved = alg_bytes / per_launch_s / 1e9
     traffic = load_traffic(args.workload, alg_bytes)
@@ -172,7 +182,9 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": wl["kernel"], "alg_bytes_per_launch": alg_bytes,
-                     "avg_launch_us": per_launch_s * 1e6},
+                     "avg_launch_us": per_launch_s * 1e6,
+                     "launch_timing": "HIP events on the step stream around the K timed steps, / K",
+                     "single_launch_us": per_launch_ms * 1e3},
         "cpu_baseline": None,
     }
     if not args.no_cpu_baseline:

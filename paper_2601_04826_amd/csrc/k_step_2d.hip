@@ -247,9 +247,15 @@ __global__ __launch_bounds__(kBlock) void k_step_2d(StepArgs a)
     const double dt = step_dt(a);
     if (blockIdx.x == 0 && threadIdx.x == 0) slot_update(a, dt);
     const int lane = threadIdx.x & (kWave - 1);
-    const int wave = (blockIdx.x * kBlock + threadIdx.x) >> 6;
     const int nsx = (a.nx + kOut - 1) / kOut;
     const int nsy = (a.ny + a.rows - 1) / a.rows;
+    // XCD-aware order: blocks are dealt round-robin to the kXcd dies, so block b
+    // runs on die b % kXcd.  Give each die one contiguous range of (strip,
+    // band) pairs so the halo rows two bands share stay in that die's L2.
+    const int nblk = (int)gridDim.x;
+    const int per_xcd = (nblk + kXcd - 1) / kXcd;
+    const int slot = (int)(blockIdx.x % kXcd) * per_xcd + (int)(blockIdx.x / kXcd);
+    const int wave = slot * (kBlock / kWave) + (threadIdx.x >> 6);
     double rmax = 0.0;
     if (wave < nsx * nsy) {  // waves beyond the grid only join the reduction
         const int sx = wave % nsx;
@@ -296,7 +302,9 @@ hipError_t launch_step_2d(int level, const StepArgs &a, hipStream_t s)
 {
     const int64_t nsx = (a.nx + kOut - 1) / kOut;
     const int64_t nsy = (a.ny + a.rows - 1) / a.rows;
-    const unsigned grid = blocks_for(nsx * nsy * kWave);
+    // whole dies' worth of blocks, so the die-major slot order covers every wave
+    const int64_t blocks = (nsx * nsy * kWave + kBlock - 1) / kBlock;
+    const unsigned grid = (unsigned)((blocks + kXcd - 1) / kXcd * kXcd);
 #define L2(N) hipLaunchKernelGGL(k_step_2d<N>, dim3(grid), dim3(kBlock), 0, s, a)
     SME_LEVEL_SWITCH(level, L2)
 #undef L2

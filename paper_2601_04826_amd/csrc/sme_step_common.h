@@ -32,6 +32,7 @@ namespace detail {
 constexpr int kWave = 64;
 constexpr int kBlock = 256;
 constexpr int kOut = kWave - 2;  // outputs per wave along x
+constexpr int kXcd = 8;          // compute dies (XCDs) of the MI355X, each with its own L2
 
 __device__ __forceinline__ double step_dt(const StepArgs &a)
 {
