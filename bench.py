@@ -42,6 +42,8 @@ WORKLOADS = {
     "dam_break_1d": dict(gen="dam_break_1d", args={}, kernel="k_step_1d", name="dam_break_1d_1000_level1"),
     "struct_2d_4096_l2": dict(gen="struct_2d", args=dict(n=4096), kernel="k_step_2d",
                               name="struct_2d_4096x4096_level2_periodic"),
+    "batch_512": dict(gen="batch", args={}, kernel="k_batch_step",
+                      name="batch_512_grids_side64-512_levels1-4_walls"),
 }
 
 
@@ -93,6 +95,7 @@ def main():
     ap.add_argument("--workload", default="struct_2d_1024_l2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-tune", action="store_true", help="batch: skip the tile autotuner")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (read + write), 5 times: "
                          "calibrates the HBM byte counters against a kernel of known traffic")
@@ -121,6 +124,8 @@ def main():
         print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8, "launches": 5}))
         return
     wl = WORKLOADS[args.workload]
+    if wl["gen"] == "batch":
+        return bench_batch(args, wl, torch, sme, workloads)
     t0 = time.perf_counter()
     problem = getattr(workloads, wl["gen"])(**wl["args"])
     print(f"[bench] workload {wl['name']}: {problem['ncells']} cells, level {problem['level']} "
@@ -189,6 +194,64 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(problem, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+def bench_batch(args, wl, torch, sme, workloads):
+    """The ensemble: every grid advances one step per launch (its own CFL step)."""
+    t0 = time.perf_counter()
+    probs = workloads.batch()
+    cells = sum(p["ncells"] for p in probs)
+    print(f"[bench] workload {wl['name']}: {len(probs)} grids, {cells} cells "
+          f"(generated in {time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
+    stream = torch.cuda.Stream()
+    bt = sme.Batch(probs, stream=stream.cuda_stream)
+    cache = os.environ.get("SME_TUNE_CACHE")
+    if not args.no_tune:
+        bt.autotune(cache)
+    print("[bench] band rows per level: " + ", ".join(f"L{l}={bt.rows(l)}" for l in range(5)), file=sys.stderr,
+          flush=True)
+    for i, p in enumerate(probs):
+        bt.set_state(i, p["q"])
+    torch.cuda.synchronize()
+    bt.run(args.warmup)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    bt.run(args.steps)  # synchronises at the end (error check), after ev1 is queued below
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    bt.close()
+    value = cells * args.steps / (ms * 1e-3)
+    alg = sum(bytes_per_cell(p["kind"], p["level"]) * p["ncells"] for p in probs)
+    per_launch_s = ms * 1e-3 / args.steps
+    out = {
+        "metric": "SME cell-updates/s (FP64)", "value": value, "unit": "cell-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": wl["name"], "grids": len(probs), "cells": cells,
+                   "levels": sorted({p["level"] for p in probs})},
+        "roofline": {"bound": "hbm", "achieved": alg / per_launch_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": alg / per_launch_s / 1e9 / HBM_PEAK_GBS, "traffic": load_traffic(args.workload, alg),
+                     "kernel": wl["kernel"], "alg_bytes_per_launch": alg, "avg_launch_us": per_launch_s * 1e6,
+                     "launch_timing": "HIP events on the step stream around the K timed steps, / K"},
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        # the oracle on a bounded sample: whole grids of the ensemble, first step each
+        from oracle import sme as orc
+
+        done, t0 = 0, time.perf_counter()
+        for p in probs:
+            orc.from_problem(p).step(p["q"])
+            done += p["ncells"]
+            if time.perf_counter() - t0 > args.cpu_seconds:
+                break
+        el = time.perf_counter() - t0
+        out["cpu_baseline"] = dict(value=done / el, unit="cell-updates/s", cores=orc.max_threads(), kind="oracle",
+                                   sample=f"one step of the first {done} cells of the ensemble ({el:.1f} s)")
     print(json.dumps(out), flush=True)
 
 

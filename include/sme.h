@@ -144,6 +144,40 @@ int sme_level(const sme_ctx *ctx);
 const double *sme_state_device(const sme_ctx *ctx);
 int64_t sme_field_stride(const sme_ctx *ctx);
 
+/* ------------------------------------------------------------------------
+ * Batched ensemble: n independent structured 2D grids (SME_MESH_2D_STRUCT) of
+ * mixed size and level 0..4, advanced together by one persistent kernel launch
+ * per step (captured in HIP graphs); every grid takes its own CFL step (the
+ * adaptive step of Sec. 3.1 per grid).  The model parameters are shared.
+ * Each grid's state is handled in its own caller order, [nfields_i][nx_i*ny_i].
+ * A grid advanced in a batch is bitwise identical to the same grid advanced
+ * alone by sme_run.  Errors as above; sme_batch_last_error gives the text.
+ */
+typedef struct sme_batch sme_batch;
+
+/* levels[i] in 0..4, meshes[i] structured; b NULL or b[i] NULL = flat bed,
+ * else b[i] host array [nx_i*ny_i].  stream as for sme_init. */
+int sme_batch_init(sme_batch **out, int n, const int *levels, const sme_mesh *meshes,
+                   const double *const *b, const sme_params *params, void *stream);
+int sme_batch_set_state(sme_batch *bt, int inst, const double *q, int on_device);
+int sme_batch_get_state(sme_batch *bt, int inst, double *q, int on_device);
+/* n_steps steps of every grid; if any grid produced h <= 0 or a non-finite
+ * value the call returns SME_ENONPHYS (it synchronises the stream). */
+int sme_batch_run(sme_batch *bt, int64_t n_steps);
+int sme_batch_time(sme_batch *bt, int inst, double *t, int64_t *steps);
+int64_t sme_batch_cells(const sme_batch *bt);
+/* Band height (rows per wave) used for grids of a level, and setting it. */
+int sme_batch_rows(const sme_batch *bt, int level);
+int sme_batch_set_rows(sme_batch *bt, int level, int rows);
+/* Tile autotuner: for every level present, times candidate band heights on
+ * this device with HIP events and keeps the fastest; results are cached in the
+ * text file cache_path (NULL = no cache) keyed by device name, compute-unit
+ * count, level and grid mix.  Call before loading states: it overwrites the
+ * states with a lake at rest and resets every clock. */
+int sme_batch_autotune(sme_batch *bt, const char *cache_path);
+const char *sme_batch_last_error(const sme_batch *bt);
+void sme_batch_destroy(sme_batch *bt);
+
 /* Introspection, host only (no device work): the FP64 basis tensors the kernels
  * are compiled with (Eq. (1), Sec. 3.4): M[n], A[n*n*n], B[n*n*n], K[n*n] with
  * n = level + 1, A[(i*n + j)*n + k] = <phi_i phi_j, phi_k>,

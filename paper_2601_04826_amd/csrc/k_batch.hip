@@ -1,0 +1,88 @@
+// k_batch.hip -- many structured SME grids of mixed size and level advanced by
+// one persistent launch per step.
+//
+// The work list holds one item per (grid, strip, band), sorted by level
+// (costliest first) so that the static round-robin deal over the resident
+// waves gives every wave a similar mix.  Each grid keeps its own three time
+// slots, so every grid takes its own CFL step; the item holding the grid's
+// first band also advances that grid's clock.  The band code is the one of the
+// single-grid kernel, so a grid advanced here is bitwise identical to the same
+// grid advanced alone.
+#include <hip/hip_runtime.h>
+
+#include "sme_band2d.h"
+
+namespace sme {
+
+using namespace detail;
+
+namespace {
+
+__global__ __launch_bounds__(kBlock) void k_batch_step(BatchArgs B)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int nwaves = (int)gridDim.x * (kBlock / kWave);
+    const int w = __builtin_amdgcn_readfirstlane((int)blockIdx.x * (kBlock / kWave) + (int)(threadIdx.x >> 6));
+    for (int it = w; it < B.nitems; it += nwaves) {
+        const BatchItem item = B.items[it];
+        const BatchInst I = B.inst[item.inst];
+        StepArgs a;
+        a.q = B.q + I.offset;
+        a.qn = B.qn + I.offset;
+        a.b = B.b + I.boff;
+        a.stride = I.stride;
+        a.ncells = (int64_t)I.nx * I.ny;
+        a.nx = I.nx;
+        a.ny = I.ny;
+        a.idx = I.idx;
+        a.idy = I.idy;
+        a.bc[0] = I.bc[0];
+        a.bc[1] = I.bc[1];
+        a.bc[2] = I.bc[2];
+        a.bc[3] = I.bc[3];
+        a.rows = I.rows;
+        a.nbr = nullptr;
+        a.fnx = a.fny = a.fw = nullptr;
+        a.g = B.g;
+        a.c_slip = B.c_slip;
+        a.nu = B.nu;
+        a.cfl = B.cfl;
+        a.quad = B.quad;
+        a.dt_fixed = 0.0;
+        a.t_end = 0.0;
+        a.slots = B.slots + 3 * item.inst;
+        a.sa = B.sa;
+        a.sb = B.sb;
+        a.sc = B.sc;
+        a.err = B.err;
+        const double dt = step_dt(a);
+        if (item.sx == 0 && item.sy == 0 && lane == 0) slot_update(a, dt);
+        double r = 0.0;
+        switch (I.level) {
+        case 0: r = band2d<0>(a, dt, item.sx, item.sy); break;
+        case 1: r = band2d<1>(a, dt, item.sx, item.sy); break;
+        case 2: r = band2d<2>(a, dt, item.sx, item.sy); break;
+        case 3: r = band2d<3>(a, dt, item.sx, item.sy); break;
+        case 4: r = band2d<4>(a, dt, item.sx, item.sy); break;
+        default: break;
+        }
+        r = wave_max(r);
+        if (lane == 0 && r > 0.0) atomicMax(&a.slots[a.sb].rbits, (unsigned long long)__double_as_longlong(r));
+    }
+}
+
+}  // namespace
+
+hipError_t launch_batch_step(const BatchArgs &a, int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_batch_step, dim3(grid), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+int batch_vgprs()
+{
+    hipFuncAttributes fa{};
+    return hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(&k_batch_step)) == hipSuccess ? fa.numRegs : -1;
+}
+
+}  // namespace sme

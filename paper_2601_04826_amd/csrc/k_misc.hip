@@ -62,8 +62,10 @@ __global__ void k_slots_reset(Slot *slots, ErrWord *err, int sa)
             slots[s].dt = 0.0;
             slots[s].step = 0;
         }
-        err->flag = 0u;
-        err->first_step = ~0ull;
+        if (err) {
+            err->flag = 0u;
+            err->first_step = ~0ull;
+        }
     }
 }
 

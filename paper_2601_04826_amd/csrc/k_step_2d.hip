@@ -1,20 +1,7 @@
 // k_step_2d.hip -- SME step on structured 2D grids (one launch per step).
-//
-// Fields (h, qx_0..qx_N, qy_0..qy_N), cell index j * nx + i.  A 64-lane wave
-// owns 64 consecutive columns (62 outputs and one halo column on each side) of
-// a band of `rows` rows and marches up the band:
-//   * each cell's flux is evaluated once for both directions; the x-frame and
-//     y-frame tangential blocks are the same quadratic form (A is symmetric);
-//   * each lane computes the x-face to its right; the right cell's share moves
-//     one lane up through a cross-lane shuffle;
-//   * the y-face between the previous and the current row is computed once,
-//     with the previous row held in registers (two register sets that swap
-//     roles every row, so nothing is copied);
-//   * rows are loaded one at a time (registers go to occupancy, three waves per
-//     SIMD at level 2, rather than to a prefetched row).
 #include <hip/hip_runtime.h>
 
-#include "sme_step_common.h"
+#include "sme_band2d.h"
 
 namespace sme {
 
@@ -23,230 +10,10 @@ using namespace detail;
 namespace {
 
 template <int N>
-struct Cell2 {
-    static constexpr int n = N + 1;
-    double h, b;
-    double qx[n], qy[n];  // state as loaded (ghosts mirrored)
-    double Fxx[n];        // x-frame normal block (x momenta), gravity included
-    double Fyy[n];        // y-frame normal block (y momenta), gravity included
-    double Ft[n];         // tangential block, identical in both frames
-    double lx, ly;        // wave-speed bounds along x and y
-};
-
-template <int N>
-struct Raw2 {
-    double h, b;
-    double qx[N + 1], qy[N + 1];
-};
-
-template <int N>
-__device__ __forceinline__ void load_raw(const StepArgs &a, int row, bool my, int col, bool mx, Raw2<N> &r)
-{
-    constexpr int n = N + 1;
-    const int64_t cell = (int64_t)row * a.nx + col;
-    r.h = a.q[cell];
-    r.b = a.b[cell];
-#pragma unroll
-    for (int k = 0; k < n; ++k) {
-        const double vx = a.q[(1 + k) * a.stride + cell];
-        const double vy = a.q[(1 + n + k) * a.stride + cell];
-        r.qx[k] = mx ? -vx : vx;
-        r.qy[k] = my ? -vy : vy;
-    }
-}
-
-template <int N>
-__device__ __forceinline__ void load_row(const StepArgs &a, int j, int col, bool mx, Raw2<N> &r)
-{
-    bool my;
-    const int row = ghost_index(j, a.ny, a.bc[2], a.bc[3], my);
-    load_raw<N>(a, row, my, col, mx, r);
-}
-
-template <int N>
-__device__ __forceinline__ void cell_flux(Cell2<N> &c, const Raw2<N> &r, double g)
-{
-    constexpr int n = N + 1;
-    c.h = r.h;
-    c.b = r.b;
-#pragma unroll
-    for (int k = 0; k < n; ++k) {
-        c.qx[k] = r.qx[k];
-        c.qy[k] = r.qy[k];
-    }
-    const double ih = rcp(c.h);
-    double al[n], be[n];
-#pragma unroll
-    for (int k = 0; k < n; ++k) {
-        al[k] = c.qx[k] * ih;
-        be[k] = c.qy[k] * ih;
-    }
-    quad_form<N>(c.qx, al, c.Fxx);
-    quad_form<N>(c.qy, be, c.Fyy);
-    quad_form<N>(c.qx, be, c.Ft);
-    const double gh = g * c.h;
-    const double p = 0.5 * gh * c.h;
-    c.Fxx[0] += p;
-    c.Fyy[0] += p;
-    c.lx = lam_bound<N>(gh, al);
-    c.ly = lam_bound<N>(gh, be);
-}
-
-template <int N>
-__device__ __forceinline__ void x_side(const Cell2<N> &c, Side<N, true> &s)
-{
-    s.h = c.h;
-    s.b = c.b;
-#pragma unroll
-    for (int k = 0; k <= N; ++k) {
-        s.qa[k] = c.qx[k];
-        s.qt[k] = c.qy[k];
-        s.Fa[k] = c.Fxx[k];
-        s.Ft[k] = c.Ft[k];
-    }
-    s.lam = c.lx;
-}
-
-template <int N>
-__device__ __forceinline__ void y_side(const Cell2<N> &c, Side<N, true> &s)
-{
-    s.h = c.h;
-    s.b = c.b;
-#pragma unroll
-    for (int k = 0; k <= N; ++k) {
-        s.qa[k] = c.qy[k];
-        s.qt[k] = c.qx[k];
-        s.Fa[k] = c.Fyy[k];
-        s.Ft[k] = c.Ft[k];
-    }
-    s.lam = c.ly;
-}
-
-// y-face between P (below) and C (above), normal +y.  Adds P's share to accP
-// and sets accC to C's share; both in physical field order, scaled by 1/dy.
-template <int N>
-__device__ __forceinline__ void y_face(const StepArgs &a, const Cell2<N> &P, const Cell2<N> &C, double *accP,
-                                       double *accC, bool add_p)
-{
-    constexpr int n = N + 1;
-    Side<N, true> L, R;
-    y_side<N>(P, L);
-    y_side<N>(C, R);
-    double Fh[2 * n + 1], D[2 * n + 1];
-    face_flux<N, true>(L, R, a.g, a.quad, Fh, D);
-    // frame [h, y.., x..] -> physical [h, x.., y..]
-    if (add_p) {
-        accP[0] = fma(a.idy, fma(0.5, D[0], Fh[0]), accP[0]);
-#pragma unroll
-        for (int k = 0; k < n; ++k) {
-            accP[1 + n + k] = fma(a.idy, fma(0.5, D[1 + k], Fh[1 + k]), accP[1 + n + k]);
-            accP[1 + k] = fma(a.idy, fma(0.5, D[1 + n + k], Fh[1 + n + k]), accP[1 + k]);
-        }
-    }
-    if (accC) {
-        accC[0] = a.idy * fma(0.5, D[0], -Fh[0]);
-#pragma unroll
-        for (int k = 0; k < n; ++k) {
-            accC[1 + n + k] = a.idy * fma(0.5, D[1 + k], -Fh[1 + k]);
-            accC[1 + k] = a.idy * fma(0.5, D[1 + n + k], -Fh[1 + n + k]);
-        }
-    }
-}
-
-// x-faces of the row of C: face to the right of each lane, neighbour via shuffle.
-template <int N>
-__device__ __forceinline__ void x_faces(const StepArgs &a, const Cell2<N> &C, double *accC)
-{
-    constexpr int n = N + 1;
-    constexpr int nf = 2 * n + 1;
-    Side<N, true> X, R;
-    x_side<N>(C, X);
-    R.h = shfl_dn(X.h);
-    R.b = shfl_dn(X.b);
-    R.lam = shfl_dn(X.lam);
-#pragma unroll
-    for (int k = 0; k < n; ++k) {
-        R.qa[k] = shfl_dn(X.qa[k]);
-        R.qt[k] = shfl_dn(X.qt[k]);
-        R.Fa[k] = shfl_dn(X.Fa[k]);
-        R.Ft[k] = shfl_dn(X.Ft[k]);
-    }
-    double Gh[nf], E[nf];
-    face_flux<N, true>(X, R, a.g, a.quad, Gh, E);
-#pragma unroll
-    for (int f = 0; f < nf; ++f) {
-        const double own = fma(0.5, E[f], Gh[f]);
-        const double oth = fma(0.5, E[f], -Gh[f]);
-        accC[f] = fma(a.idx, own + shfl_up1(oth), accC[f]);
-    }
-}
-
-// predictor, friction, store, CFL ratio of the new state
-template <int N>
-__device__ __forceinline__ double finish_cell(const StepArgs &a, double dt, int64_t cell, bool out,
-                                              const Cell2<N> &c, const double *acc)
-{
-    constexpr int n = N + 1;
-    const double h = fma(-dt, acc[0], c.h);
-    double qx[n], qy[n];
-#pragma unroll
-    for (int k = 0; k < n; ++k) {
-        qx[k] = fma(-dt, acc[1 + k], c.qx[k]);
-        qy[k] = fma(-dt, acc[1 + n + k], c.qy[k]);
-    }
-    const double ih = rcp(h);
-    friction<N>(qx, ih, dt, a.c_slip, a.nu);
-    friction<N>(qy, ih, dt, a.c_slip, a.nu);
-    double r = 0.0;
-    if (out) {
-        a.qn[cell] = h;
-        double sum = h;
-#pragma unroll
-        for (int k = 0; k < n; ++k) {
-            a.qn[(1 + k) * a.stride + cell] = qx[k];
-            a.qn[(1 + n + k) * a.stride + cell] = qy[k];
-            sum += qx[k] + qy[k];
-        }
-        flag_bad(a, !(h > 0.0) || !isfinite(sum));
-        double lm;
-        r = cfl_ratio_2d<N>(a.g, h, ih, qx, qy, a.idx, a.idy, &lm);
-        if (!(r >= 0.0)) r = 0.0;
-    }
-    return r;
-}
-
-// one row: C <- row j (state in `raw`), y-face with P, finish P (row j-1) if
-// requested, x-faces of C.
-template <int N>
-__device__ __forceinline__ void row(const StepArgs &a, double dt, Cell2<N> &P, double *accP, Cell2<N> &C,
-                                    double *accC, const Raw2<N> &raw, int j, int c, bool outc, bool finish_p,
-                                    double &rmax)
-{
-    cell_flux<N>(C, raw, a.g);
-    y_face<N>(a, P, C, accP, accC, finish_p);
-    if (finish_p) rmax = fmax(rmax, finish_cell<N>(a, dt, (int64_t)(j - 1) * a.nx + c, outc, P, accP));
-    x_faces<N>(a, C, accC);
-}
-
-// closing y-face of the band: P is the last row (j1 - 1), raw the row above
-template <int N>
-__device__ __forceinline__ void close_band(const StepArgs &a, double dt, Cell2<N> &P, double *accP,
-                                           Cell2<N> &G, const Raw2<N> &raw, int j1, int c, bool outc,
-                                           double &rmax)
-{
-    cell_flux<N>(G, raw, a.g);
-    y_face<N>(a, P, G, accP, nullptr, true);
-    rmax = fmax(rmax, finish_cell<N>(a, dt, (int64_t)(j1 - 1) * a.nx + c, outc, P, accP));
-}
-
-template <int N>
 __global__ __launch_bounds__(kBlock) void k_step_2d(StepArgs a)
 {
-    constexpr int n = N + 1;
-    constexpr int nf = 2 * n + 1;
     const double dt = step_dt(a);
     if (blockIdx.x == 0 && threadIdx.x == 0) slot_update(a, dt);
-    const int lane = threadIdx.x & (kWave - 1);
     const int nsx = (a.nx + kOut - 1) / kOut;
     const int nsy = (a.ny + a.rows - 1) / a.rows;
     // XCD-aware order: blocks are dealt round-robin to the kXcd dies, so block b
@@ -257,42 +24,8 @@ __global__ __launch_bounds__(kBlock) void k_step_2d(StepArgs a)
     const int slot = (int)(blockIdx.x % kXcd) * per_xcd + (int)(blockIdx.x / kXcd);
     const int wave = slot * (kBlock / kWave) + (threadIdx.x >> 6);
     double rmax = 0.0;
-    if (wave < nsx * nsy) {  // waves beyond the grid only join the reduction
-        const int sx = wave % nsx;
-        const int sy = wave / nsx;
-        const int c = sx * kOut - 1 + lane;
-        const int j0 = sy * a.rows;
-        const int j1 = min(j0 + a.rows, a.ny);
-        bool mx;
-        const int col = ghost_index(c, a.nx, a.bc[0], a.bc[1], mx);
-        const bool outc = lane >= 1 && lane <= kOut && c < a.nx;
-
-        Cell2<N> A, B;
-        double accA[nf], accB[nf];
-        Raw2<N> nxt;
-        load_row<N>(a, j0 - 1, col, mx, nxt);
-        cell_flux<N>(A, nxt, a.g);  // halo row below the band
-#pragma unroll
-        for (int f = 0; f < nf; ++f) accA[f] = 0.0;
-        load_row<N>(a, j0, col, mx, nxt);
-        int j = j0;
-        while (true) {
-            Raw2<N> cur = nxt;
-            row<N>(a, dt, A, accA, B, accB, cur, j, c, outc, j > j0, rmax);
-            load_row<N>(a, j + 1, col, mx, nxt);
-            if (++j == j1) {
-                close_band<N>(a, dt, B, accB, A, nxt, j1, c, outc, rmax);
-                break;
-            }
-            cur = nxt;
-            row<N>(a, dt, B, accB, A, accA, cur, j, c, outc, true, rmax);
-            load_row<N>(a, j + 1, col, mx, nxt);
-            if (++j == j1) {
-                close_band<N>(a, dt, A, accA, B, nxt, j1, c, outc, rmax);
-                break;
-            }
-        }
-    }
+    if (wave < nsx * nsy)  // waves beyond the grid only join the reduction
+        rmax = band2d<N>(a, dt, wave % nsx, wave / nsx);
     publish_max(&a.slots[a.sb].rbits, rmax);
 }
 

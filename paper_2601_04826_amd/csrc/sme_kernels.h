@@ -55,13 +55,48 @@ struct StepArgs {
     ErrWord *err;
 };
 
-// host-side launchers (defined in sme_kernels.hip); level is 0..8
+// ---------------------------------------------------------------------------
+// Batched ensemble: many structured grids advanced by one persistent launch.
+constexpr int kBatchMaxLevel = 4;
+
+struct BatchInst {
+    int level;
+    int nx, ny, rows;
+    int bc[4];
+    int64_t offset;   // element offset of field 0 of this grid in the state arenas
+    int64_t stride;   // field stride of this grid (elements)
+    int64_t boff;     // element offset of its bathymetry
+    double idx, idy;  // 1/dx, 1/dy
+};
+
+struct BatchItem {
+    int inst, sx, sy, pad;  // one wave's work: strip sx, band sy of grid inst
+};
+
+struct BatchArgs {
+    const double *q;
+    double *qn;
+    const double *b;
+    const BatchInst *inst;
+    const BatchItem *items;
+    int nitems;
+    Slot *slots;       // [n_inst][3]
+    int sa, sb, sc;
+    ErrWord *err;
+    double g, c_slip, nu, cfl;
+    Quad quad;
+};
+
+hipError_t launch_batch_step(const BatchArgs &a, int grid, hipStream_t s);
+int batch_vgprs();
+
+// host-side launchers; level is 0..8
 hipError_t launch_step_1d(int level, const StepArgs &a, hipStream_t s);
 hipError_t launch_step_2d(int level, const StepArgs &a, hipStream_t s);
 int step_2d_vgprs(int level);  // registers per lane of the structured step kernel, -1 on error
 hipError_t launch_step_tri(int level, const StepArgs &a, hipStream_t s);
 hipError_t launch_eig(int dim, int kind, int level, const StepArgs &a, hipStream_t s);
-hipError_t launch_slots_reset(Slot *slots, ErrWord *err, int sa, hipStream_t s);
+hipError_t launch_slots_reset(Slot *slots, ErrWord *err, int sa, hipStream_t s);  // err may be null
 hipError_t launch_permute(const double *src, int64_t sstride, double *dst, int64_t dstride,
                           const int64_t *map, int64_t ncells, int nf, hipStream_t s);
 

@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "../../include/sme.h"
+#include "sme_host.h"
 #include "sme_kernels.h"
 
 using namespace sme;
@@ -87,45 +88,6 @@ int fail(sme_ctx *c, int code, const char *fmt, ...)
     } while (0)
 
 int nfields_of(int level, int kind) { return kind == SME_MESH_1D ? level + 2 : 2 * level + 3; }
-
-// Gauss-Legendre points on [0, 1] (weights sum to 1) by Newton's method on P_n.
-void gauss_legendre01(int n, double *s, double *w)
-{
-    for (int i = 0; i < n; ++i) {
-        long double x = cosl(3.14159265358979323846264338327950288L * (i + 0.75L) / (n + 0.5L));
-        long double dp = 0;
-        for (int it = 0; it < 100; ++it) {
-            long double p0 = 1, p1 = x;
-            for (int k = 2; k <= n; ++k) {
-                long double p2 = ((2 * k - 1) * x * p1 - (k - 1) * p0) / k;
-                p0 = p1;
-                p1 = p2;
-            }
-            if (n == 1) {
-                p1 = x;
-                p0 = 1;
-            }
-            dp = n * (x * p1 - p0) / (x * x - 1);
-            long double dx = p1 / dp;
-            x -= dx;
-            if (fabsl(dx) < 1e-30L) break;
-        }
-        long double p0 = 1, p1 = x;
-        for (int k = 2; k <= n; ++k) {
-            long double p2 = ((2 * k - 1) * x * p1 - (k - 1) * p0) / k;
-            p0 = p1;
-            p1 = p2;
-        }
-        if (n == 1) {
-            p1 = x;
-            p0 = 1;
-        }
-        dp = n * (x * p1 - p0) / (x * x - 1);
-        long double wi = 2.0L / ((1 - x * x) * dp * dp);
-        s[i] = (double)(0.5L * (1.0L - x));
-        w[i] = (double)(0.5L * wi);
-    }
-}
 
 int check_mesh(const sme_mesh *m, int level, int *nf, int64_t *nc)
 {
@@ -294,12 +256,8 @@ std::vector<int64_t> rcm_order(const std::vector<int32_t> &nbr, int64_t n)
 // generations x (rows + 1.5) for this grid, level and device.
 int pick_rows(int level, int64_t nx, int64_t ny)
 {
-    int dev = 0, cus = 256;
-    hipDeviceProp_t prop;
-    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
-        cus = std::max(1, prop.multiProcessorCount);
-    const int regs = step_2d_vgprs(level);
-    const int per_simd = regs > 0 ? std::max(1, std::min(8, 512 / ((regs + 7) / 8 * 8))) : 2;
+    const int cus = host::device_cus();
+    const int per_simd = host::waves_per_simd(step_2d_vgprs(level));
     const int64_t slots = (int64_t)cus * 4 * per_simd;
     const int64_t nsx = (nx + 61) / 62;
     int best = 8;
@@ -479,7 +437,7 @@ int sme_init(sme_ctx **out, int level, const sme_mesh *mesh, const sme_params *p
     c->stride = (nc + 255) / 256 * 256;
     c->p = *params;
     double qs[kMaxQuad] = {0}, qw[kMaxQuad] = {0};
-    gauss_legendre01(params->quad_points, qs, qw);
+    host::gauss_legendre01(params->quad_points, qs, qw);
     c->quad.n = params->quad_points;
     c->quad.s0 = qs[0];
     c->quad.s1 = qs[1];

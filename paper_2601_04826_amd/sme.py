@@ -29,6 +29,9 @@ EXPORTS = [
     "sme_run", "sme_time", "sme_nfields", "sme_ncells", "sme_level", "sme_state_device",
     "sme_field_stride",
     "sme_basis_tensors", "sme_strerror", "sme_last_error", "sme_destroy",
+    "sme_batch_init", "sme_batch_set_state", "sme_batch_get_state", "sme_batch_run", "sme_batch_time",
+    "sme_batch_cells", "sme_batch_rows", "sme_batch_set_rows", "sme_batch_autotune",
+    "sme_batch_last_error", "sme_batch_destroy",
 ]
 
 
@@ -75,6 +78,17 @@ def _load():
         "sme_strerror": (ctypes.c_char_p, [i]),
         "sme_last_error": (ctypes.c_char_p, [vp]),
         "sme_destroy": (None, [vp]),
+        "sme_batch_init": (i, [P(vp), i, vp, vp, vp, vp, vp]),
+        "sme_batch_set_state": (i, [vp, i, vp, i]),
+        "sme_batch_get_state": (i, [vp, i, vp, i]),
+        "sme_batch_run": (i, [vp, i64]),
+        "sme_batch_time": (i, [vp, i, P(d), P(i64)]),
+        "sme_batch_cells": (i64, [vp]),
+        "sme_batch_rows": (i, [vp, i]),
+        "sme_batch_set_rows": (i, [vp, i, i]),
+        "sme_batch_autotune": (i, [vp, ctypes.c_char_p]),
+        "sme_batch_last_error": (ctypes.c_char_p, [vp]),
+        "sme_batch_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -251,6 +265,81 @@ class Solver:
     def close(self):
         if self.ctx:
             sme_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _bcheck(code, bt):
+    if code != SME_OK:
+        msg = _lib.sme_strerror(code).decode()
+        detail = _lib.sme_batch_last_error(bt).decode() if bt else ""
+        raise SmeError(code, f"{msg}: {detail}" if detail else msg)
+
+
+class Batch:
+    """Batched ensemble of structured grids (levels 0..4) advanced together by
+    one persistent launch per step, each grid with its own CFL step."""
+
+    def __init__(self, problems, stream=None, **param_overrides):
+        p = dict(problems[0]["params"])
+        p.update(param_overrides)
+        self.params = make_params(**p)
+        n = len(problems)
+        self.n = n
+        meshes = (sme_mesh * n)()
+        for k, pr in enumerate(problems):
+            if pr["kind"] != "2d":
+                raise ValueError("batched grids must be structured 2D")
+            m, _ = make_mesh(pr)
+            meshes[k] = m
+        levels = (ctypes.c_int * n)(*[pr["level"] for pr in problems])
+        self._b = [np.ascontiguousarray(pr["b"], dtype=np.float64) if pr.get("b") is not None else None
+                   for pr in problems]
+        bptr = (ctypes.c_void_p * n)(*[x.ctypes.data if x is not None else None for x in self._b])
+        if stream is None and torch.cuda.is_available():
+            stream = torch.cuda.current_stream().cuda_stream
+        self.ctx = ctypes.c_void_p()
+        _bcheck(_lib.sme_batch_init(ctypes.byref(self.ctx), n, levels, meshes, bptr, ctypes.byref(self.params),
+                                    ctypes.c_void_p(stream or 0)), None)
+        self.shapes = [(pr["q"].shape[0], pr["ncells"]) for pr in problems]
+        self.cells = _lib.sme_batch_cells(self.ctx)
+
+    def set_state(self, i, q):
+        q = np.ascontiguousarray(q, dtype=np.float64)
+        if q.shape != self.shapes[i]:
+            raise ValueError(f"grid {i} state must have shape {self.shapes[i]}")
+        _bcheck(_lib.sme_batch_set_state(self.ctx, i, q.ctypes.data_as(ctypes.c_void_p), 0), self.ctx)
+
+    def get_state(self, i):
+        out = np.empty(self.shapes[i])
+        _bcheck(_lib.sme_batch_get_state(self.ctx, i, out.ctypes.data_as(ctypes.c_void_p), 0), self.ctx)
+        return out
+
+    def run(self, n_steps):
+        _bcheck(_lib.sme_batch_run(self.ctx, int(n_steps)), self.ctx)
+
+    def time(self, i):
+        t, s = ctypes.c_double(), ctypes.c_int64()
+        _bcheck(_lib.sme_batch_time(self.ctx, i, ctypes.byref(t), ctypes.byref(s)), self.ctx)
+        return t.value, s.value
+
+    def rows(self, level):
+        return _lib.sme_batch_rows(self.ctx, level)
+
+    def set_rows(self, level, rows):
+        _bcheck(_lib.sme_batch_set_rows(self.ctx, level, rows), self.ctx)
+
+    def autotune(self, cache_path=None):
+        _bcheck(_lib.sme_batch_autotune(self.ctx, cache_path.encode() if cache_path else None), self.ctx)
+
+    def close(self):
+        if self.ctx:
+            _lib.sme_batch_destroy(self.ctx)
             self.ctx = None
 
     def __del__(self):

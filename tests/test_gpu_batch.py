@@ -1,0 +1,145 @@
+"""GPU tests of the batched ensemble (one persistent launch per step, per-grid
+CFL step): every grid against the CPU oracle run alone, bitwise agreement with
+the same grid advanced by the single-grid path, independent clocks, the tile
+autotuner, and a sampled check of the full 512-grid ensemble."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import sme as orc
+from paper_2601_04826_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sme():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2601_04826_amd import sme as m
+
+    return m
+
+
+def rel_linf(gpu, ref):
+    worst = 0.0
+    for f in range(ref.shape[0]):
+        scale = np.max(np.abs(ref[f]))
+        if scale == 0.0:
+            assert np.all(gpu[f] == 0.0)
+            continue
+        worst = max(worst, np.max(np.abs(gpu[f] - ref[f])) / scale)
+    return worst
+
+
+def small_batch(n=12, seed=40):
+    probs = W.batch(n_inst=n, seed=seed, steps=60, side=(40, 150), levels=(0, 4))
+    for k, p in enumerate(probs):  # some bathymetry and periodic grids too
+        rng = np.random.default_rng(100 + k)
+        if k % 3 == 1:
+            p["b"] = 0.05 * rng.uniform(size=p["ncells"])
+        if k % 4 == 2:
+            p["bc"] = ("periodic", "periodic", "wall", "wall")
+    return probs
+
+
+def test_batch_matches_oracle_per_grid(sme):
+    probs = small_batch()
+    print("batch of", len(probs), "grids, levels", [p["level"] for p in probs], flush=True)
+    bt = sme.Batch(probs)
+    for i, p in enumerate(probs):
+        bt.set_state(i, p["q"])
+    bt.run(60)
+    for i, p in enumerate(probs):
+        g = bt.get_state(i)
+        t, n = bt.time(i)
+        o = orc.from_problem(p)
+        r, t_o = o.run(p["q"], 60)
+        assert n == 60
+        assert abs(t - t_o) <= 1e-12 * t_o
+        assert rel_linf(g, r) <= 1e-10, (i, p["level"], p["nx"])
+    bt.close()
+
+
+def test_batch_bitwise_equals_single_grid(sme):
+    probs = small_batch(n=10, seed=70)
+    bt = sme.Batch(probs)
+    for lvl in range(5):
+        bt.set_rows(lvl, 3 + lvl)  # band heights differ from the single-grid choice
+    for i, p in enumerate(probs):
+        bt.set_state(i, p["q"])
+    bt.run(40)
+    times = []
+    for i, p in enumerate(probs):
+        s = sme.Solver(p)
+        s.set_state(p["q"])
+        t1, _ = s.run(40)
+        q1 = s.get_state()
+        s.close()
+        assert np.array_equal(bt.get_state(i), q1), i
+        t2, _ = bt.time(i)
+        assert t1 == t2
+        times.append(t2)
+    assert len(set(times)) > 1  # every grid keeps its own clock
+    bt.close()
+
+
+def test_batch_autotune_and_cache(sme, tmp_path):
+    probs = small_batch(n=8, seed=90)
+    bt = sme.Batch(probs)
+    cache = str(tmp_path / "tune.txt")
+    bt.autotune(cache)
+    rows = [bt.rows(l) for l in range(5)]
+    assert all(r >= 1 for r in rows)
+    assert os.path.exists(cache) and open(cache).read().strip()
+    for i, p in enumerate(probs):
+        bt.set_state(i, p["q"])
+    bt.run(12)
+    for i, p in enumerate(probs[:3]):
+        r, _ = orc.from_problem(p).run(p["q"], 12)
+        assert rel_linf(bt.get_state(i), r) <= 1e-11
+    bt.close()
+    bt2 = sme.Batch(probs)
+    bt2.autotune(cache)  # answered from the cache
+    assert [bt2.rows(l) for l in range(5)] == rows
+    bt2.close()
+
+
+def test_batch_nonphysical_reported(sme):
+    probs = small_batch(n=3, seed=5)
+    probs[1]["q"][0, 10] = -1.0
+    bt = sme.Batch(probs)
+    for i, p in enumerate(probs):
+        bt.set_state(i, p["q"])
+    with pytest.raises(sme.SmeError) as e:
+        bt.run(2)
+    assert e.value.code == sme.SME_ENONPHYS
+    bt.close()
+
+
+def test_full_ensemble_sampled(sme):
+    """The full 512-grid ensemble for 499 steps; then one more step of
+    sampled grids is compared with the oracle's step from the GPU state."""
+    probs = W.batch()
+    print("full ensemble:", sum(p["ncells"] for p in probs), "cells", flush=True)
+    bt = sme.Batch(probs)
+    for i, p in enumerate(probs):
+        bt.set_state(i, p["q"])
+    bt.run(499)
+    pick = [0, 77, 200, 311, 420, 511]
+    pre = {i: bt.get_state(i) for i in pick}
+    bt.run(1)
+    for i in pick:
+        p = probs[i]
+        o = orc.from_problem(p)
+        dt, _ = o.cfl_dt(pre[i])
+        t0, n0 = bt.time(i)
+        assert n0 == 500
+        ref, _ = o.step(pre[i], dt)
+        assert rel_linf(bt.get_state(i), ref) <= 1e-12, i
+        assert np.all(np.isfinite(ref))
+    bt.close()
