@@ -178,6 +178,52 @@ int sme_batch_autotune(sme_batch *bt, const char *cache_path);
 const char *sme_batch_last_error(const sme_batch *bt);
 void sme_batch_destroy(sme_batch *bt);
 
+/* ------------------------------------------------------------------------
+ * Learned closure: a small network (9 -> 64 -> 64 -> 2, tanh, FP32 training
+ * and inference kernels) that corrects the level-1 step towards level 8.  The
+ * paper has no learned closure; its level hierarchy (Eq. (1), Sec. 3.4) is
+ * what the network shortcuts.  Features of a cell along a direction with
+ * normal momenta (q_0, q_1): (h, q_0, q_1), their differences to the next and
+ * the previous cell along that direction.  The network maps normalised
+ * features x~ = (x - mu)/sigma to normalised rates y~; the rate of (q_0, q_1)
+ * is y~ * out_scale and the level-1 step adds dt times it.  Parameters are one
+ * FP32 array of 4930: W1[64][9], b1[64], W2[64][64], b2[64], W3[2][64], b3[2].
+ */
+typedef struct sme_mlp sme_mlp;
+
+int sme_mlp_create(sme_mlp **out, void *stream);
+int sme_mlp_set_params(sme_mlp *m, const float *params, int on_device);
+int sme_mlp_get_params(sme_mlp *m, float *params, int on_device);
+/* Normalisation (mu, sigma: 9 each), output scale (2) and the training box of
+ * the raw features (box_lo, box_hi: 9 each, FP64); outside the box a cell
+ * counts as out of range (sme_closure_out_of_range). */
+int sme_mlp_set_scaling(sme_mlp *m, const float *mu, const float *sigma, const float *out_scale,
+                        const double *box_lo, const double *box_hi);
+/* Device arrays, normalised: x [batch][9] -> y [batch][2]. */
+int sme_mlp_forward(sme_mlp *m, const float *x, int64_t batch, float *y);
+/* MSE loss L = (1/batch) sum |y~ - t~|^2 and its gradient (device, 4930;
+ * NULL skips the copy); loss into host memory (NULL: no synchronisation). */
+int sme_mlp_loss_grad(sme_mlp *m, const float *x, const float *t, int64_t batch, float *loss, float *grad);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on a batch. */
+int sme_mlp_train_step(sme_mlp *m, const float *x, const float *t, int64_t batch, float lr, float *loss);
+int sme_mlp_reset_optimizer(sme_mlp *m);
+const char *sme_mlp_last_error(const sme_mlp *m);
+void sme_mlp_destroy(sme_mlp *m);
+
+/* Training samples on a periodic 1D row (device arrays, SoA with the given
+ * field strides): raw features of cells[s] from the level-8 state q8 and
+ * targets (q_k of q8_next - q_k of q1_step) / dt, k = 0, 1, where q1_step is
+ * the level-1 step (same dt) of the first three fields of q8.
+ * feat [nsamples][9], targ [nsamples][2] (FP32). */
+int sme_closure_samples(const double *q8, int64_t stride8, const double *q8_next, int64_t stride8n,
+                        const double *q1_step, int64_t stride1, int64_t ncells, double dt,
+                        const int64_t *cells, int64_t nsamples, float *feat, float *targ, void *stream);
+/* Attach the network (copied) to a level-1 1D or structured context; NULL
+ * detaches.  Every later step adds the correction. */
+int sme_closure_attach(sme_ctx *ctx, const sme_mlp *m);
+/* Cell-steps whose features left the training box since sme_set_state. */
+int sme_closure_out_of_range(sme_ctx *ctx, int64_t *cells);
+
 /* Introspection, host only (no device work): the FP64 basis tensors the kernels
  * are compiled with (Eq. (1), Sec. 3.4): M[n], A[n*n*n], B[n*n*n], K[n*n] with
  * n = level + 1, A[(i*n + j)*n + k] = <phi_i phi_j, phi_k>,

@@ -15,7 +15,8 @@ OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsme.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
-SOURCES = ["k_step_1d.hip", "k_step_2d.hip", "k_step_tri.hip", "k_batch.hip", "k_misc.hip", "sme_lib.cpp", "sme_batch.cpp"]
+SOURCES = ["k_step_1d.hip", "k_step_2d.hip", "k_step_tri.hip", "k_batch.hip", "k_misc.hip", "k_mlp.hip",
+           "sme_lib.cpp", "sme_batch.cpp", "sme_closure.cpp"]
 FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
          # no packed FP32 instructions anywhere in the device code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -49,7 +50,7 @@ def build(jobs=None, verbose=False):
             if m.strip():
                 print(m, file=sys.stderr)
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs
+    cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-Wl,-z,defs", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}{r.stderr}")

@@ -1,0 +1,215 @@
+"""Learned closure: level 1 plus a small network standing in for level 8.
+
+Everything numeric runs in the library's kernels: the level-8 and level-1 SME
+steps that generate the data, the sample extraction (features and a-priori
+targets), the FP32 training step (forward, backward, Adam) and the inference
+fused into the level-1 step.  This module only orchestrates them; torch holds
+device buffers and does the batch shuffling.
+
+Target (a-priori closure): for consecutive level-8 states Q8^n, Q8^{n+1} with
+step dt, r = [P(Q8^{n+1}) - Step_L1(P(Q8^n))] / dt on (q_0, q_1), where P keeps
+(h, q_0, q_1) (the Legendre basis is orthogonal, so truncation is the
+projection).  Level 1 plus closure then advances Q1^{n+1} = Step_L1(Q1^n) + dt r(Q1^n).
+Outside the range of its training features the closure is not trusted: the
+level-1 run stops and the plain level-8 solver continues from the lifted state.
+"""
+import numpy as np
+import torch
+
+from . import sme, workloads
+
+N_IN, N_OUT = 9, 2
+
+
+def _project(problem8, level=1):
+    p = dict(problem8)
+    p["level"] = level
+    p["q"] = np.ascontiguousarray(problem8["q"][: level + 2])
+    return p
+
+
+def generate(seeds, n=4096, steps=2000, every=10, cells_per_snapshot=256, stream=None, rng_seed=0):
+    """Training samples from level-8 runs of the solver itself.
+
+    Returns (features [S, 9], targets [S, 2]) as float32 CUDA tensors."""
+    st = stream or torch.cuda.Stream()
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(rng_seed)
+    feats, targs = [], []
+    with torch.cuda.stream(st):
+        for seed in seeds:
+            p8 = workloads.smooth_1d(n=n, level=8, seed=seed, steps=steps)
+            s8 = sme.Solver(p8, stream=st.cuda_stream)
+            s8.set_state(p8["q"])
+            p1 = _project(p8)
+            s1 = sme.Solver(p1, stream=st.cuda_stream)
+            q8 = torch.empty((p8["q"].shape[0], n), dtype=torch.float64, device="cuda")
+            q8n = torch.empty_like(q8)
+            q1 = torch.empty((3, n), dtype=torch.float64, device="cuda")
+            for k in range(steps):
+                if k % every:
+                    s8.step(0.0)
+                    continue
+                s8.get_state(q8)
+                dt = s8.step(0.0, sync=True)
+                s8.get_state(q8n)
+                s1.set_state(q8[:3])
+                s1.step(dt)
+                s1.get_state(q1)
+                cells = torch.randperm(n, device="cuda", generator=gen)[:cells_per_snapshot]
+                f, t = sme.closure_samples(q8, q8n, q1, dt, cells, stream=st.cuda_stream)
+                feats.append(f)
+                targs.append(t)
+            s8.close()
+            s1.close()
+        st.synchronize()
+    return torch.cat(feats), torch.cat(targs)
+
+
+def init_params(seed=0):
+    """Glorot-uniform weights, zero biases (flat layout W1, b1, W2, b2, W3, b3)."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for o, i in ((64, N_IN), (64, 64), (N_OUT, 64)):
+        a = np.sqrt(6.0 / (i + o))
+        parts += [rng.uniform(-a, a, size=o * i), np.zeros(o)]
+    return np.concatenate(parts).astype(np.float32)
+
+
+class Scaling:
+    """Input normalisation, output scale and the training box of the raw features."""
+
+    def __init__(self, feat, targ, margin=0.1):
+        f = feat.double()
+        self.mu = feat.mean(0).float()
+        self.sigma = torch.clamp(feat.std(0), min=1e-6).float()
+        self.out_scale = torch.clamp(targ.std(0), min=1e-12).float()
+        lo, hi = f.min(0).values, f.max(0).values
+        span = hi - lo
+        self.box_lo = (lo - margin * span).cpu().numpy()
+        self.box_hi = (hi + margin * span).cpu().numpy()
+
+    def inputs(self, feat):
+        # same FP32 arithmetic as the kernels: (f - mu) * (1 / sigma)
+        return ((feat - self.mu) * (1.0 / self.sigma)).contiguous()
+
+    def targets(self, targ):
+        return (targ / self.out_scale).contiguous()
+
+    def apply(self, mlp):
+        mlp.set_scaling(self.mu.cpu().numpy(), self.sigma.cpu().numpy(), self.out_scale.cpu().numpy(),
+                        self.box_lo, self.box_hi)
+
+
+def fit(feat, targ, epochs=20, batch=4096, lr=2e-3, lr_end=1e-4, seed=0, stream=None, log=None):
+    """Train the network with the library's FP32 kernels (Adam, MSE on
+    normalised targets); returns (MLP, Scaling, loss history)."""
+    st = stream or torch.cuda.Stream()
+    sc = Scaling(feat, targ)
+    with torch.cuda.stream(st):
+        x = sc.inputs(feat)
+        t = sc.targets(targ)
+        mlp = sme.MLP(init_params(seed), stream=st.cuda_stream)
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(seed)
+        S = x.shape[0]
+        nb = max(1, S // batch)
+        total = epochs * nb
+        hist = []
+        step = 0
+        for ep in range(epochs):
+            perm = torch.randperm(S, device="cuda", generator=gen)
+            for b in range(nb):
+                idx = perm[b * batch:(b + 1) * batch]
+                xb = x.index_select(0, idx).contiguous()
+                tb = t.index_select(0, idx).contiguous()
+                frac = step / max(1, total - 1)
+                rate = lr * (lr_end / lr) ** frac  # geometric decay
+                want = b == nb - 1
+                loss = mlp.train_step(xb, tb, rate, want_loss=want)
+                step += 1
+            hist.append(loss)
+            if log:
+                log(f"epoch {ep + 1}/{epochs} loss {loss:.5f}")
+        sc.apply(mlp)
+        st.synchronize()
+    return mlp, sc, hist
+
+
+def relative_l1(q, q_ref, fields=(0, 1)):
+    """E_x = sum_i |x_i - x_i^ref| / sum_i |x_i^ref| for x = h and hu (equal cells)."""
+    return {f: float(np.sum(np.abs(q[f] - q_ref[f])) / np.sum(np.abs(q_ref[f]))) for f in fields}
+
+
+class ClosureSolver:
+    """Level 1 + closure on a 1D or structured grid, with the plain level-8
+    solver as fallback once a cell's features leave the training range."""
+
+    def __init__(self, problem8, mlp, chunk=50, stream=None):
+        self.p8 = problem8
+        self.mlp = mlp
+        self.chunk = chunk
+        self.stream = stream
+        self.s1 = sme.Solver(_project_any(problem8), stream=stream)
+        self.s1.attach_closure(mlp)
+        self.s8 = None
+        self.fell_back_at = None
+
+    def set_state(self, q8):
+        self.q8_init = q8
+        self.s1.set_state(_project_state(q8, self.p8))
+
+    def run_to(self, t_end, max_steps=10 ** 7):
+        """Advance to t_end; returns the final state lifted to the level-8 layout."""
+        t = 0.0
+        done = 0
+        while t < t_end and done < max_steps:
+            keep = self.s1.get_state()
+            t_keep = t
+            self.s1.set_state(keep)  # fresh clock for the chunk
+            dt_run, n = self.s1.run(self.chunk, t_end=t_end - t)
+            if self.s1.out_of_range() > 0:
+                # fall back: restart this chunk with level 8 from the lifted state
+                self.fell_back_at = t_keep
+                self.s8 = sme.Solver(self.p8, stream=self.stream)
+                self.s8.set_state(_lift_state(keep, self.p8))
+                self.s8.run(max_steps, t_end=t_end - t_keep)
+                return self.s8.get_state()
+            t += dt_run
+            done += n
+            if n == 0:
+                break
+        return _lift_state(self.s1.get_state(), self.p8)
+
+    def close(self):
+        self.s1.close()
+        if self.s8 is not None:
+            self.s8.close()
+
+
+def _project_any(problem8):
+    p = dict(problem8)
+    p["level"] = 1
+    p["q"] = _project_state(problem8["q"], problem8)
+    return p
+
+
+def _project_state(q8, problem8):
+    """(h, q_0, q_1) of each direction block of a level-8 state."""
+    if problem8["kind"] == "1d":
+        return np.ascontiguousarray(q8[:3])
+    n8 = problem8["level"] + 1
+    return np.ascontiguousarray(np.concatenate([q8[:3], q8[1 + n8:1 + n8 + 2]]))
+
+
+def _lift_state(q1, problem8):
+    """Level-1 state padded with zero higher moments to the level-8 layout."""
+    n8 = problem8["level"] + 1
+    if problem8["kind"] == "1d":
+        out = np.zeros((n8 + 1, q1.shape[1]))
+        out[:3] = q1
+        return out
+    out = np.zeros((2 * n8 + 1, q1.shape[1]))
+    out[:3] = q1[:3]
+    out[1 + n8:1 + n8 + 2] = q1[3:5]
+    return out

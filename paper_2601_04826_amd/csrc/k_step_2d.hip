@@ -9,9 +9,11 @@ using namespace detail;
 
 namespace {
 
-template <int N>
+template <int N, bool CLOS>
 __global__ __launch_bounds__(kBlock) void k_step_2d(StepArgs a)
 {
+    extern __shared__ float lds_params[];
+    if constexpr (CLOS) mlp_stage(a.closure->params, lds_params);
     const double dt = step_dt(a);
     if (blockIdx.x == 0 && threadIdx.x == 0) slot_update(a, dt);
     const int nsx = (a.nx + kOut - 1) / kOut;
@@ -25,7 +27,7 @@ __global__ __launch_bounds__(kBlock) void k_step_2d(StepArgs a)
     const int wave = slot * (kBlock / kWave) + (threadIdx.x >> 6);
     double rmax = 0.0;
     if (wave < nsx * nsy)  // waves beyond the grid only join the reduction
-        rmax = band2d<N>(a, dt, wave % nsx, wave / nsx);
+        rmax = band2d<N, CLOS>(a, dt, wave % nsx, wave / nsx, lds_params);
     publish_max(&a.slots[a.sb].rbits, rmax);
 }
 
@@ -38,7 +40,12 @@ hipError_t launch_step_2d(int level, const StepArgs &a, hipStream_t s)
     // whole dies' worth of blocks, so the die-major slot order covers every wave
     const int64_t blocks = (nsx * nsy * kWave + kBlock - 1) / kBlock;
     const unsigned grid = (unsigned)((blocks + kXcd - 1) / kXcd * kXcd);
-#define L2(N) hipLaunchKernelGGL(k_step_2d<N>, dim3(grid), dim3(kBlock), 0, s, a)
+    if (a.closure) {
+        if (level != 1) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_step_2d<1, true>), dim3(grid), dim3(kBlock), kMlpParams * sizeof(float), s, a);
+        return hipGetLastError();
+    }
+#define L2(N) hipLaunchKernelGGL((k_step_2d<N, false>), dim3(grid), dim3(kBlock), 0, s, a)
     SME_LEVEL_SWITCH(level, L2)
 #undef L2
     return hipGetLastError();
@@ -48,7 +55,7 @@ int step_2d_vgprs(int level)
 {
     hipFuncAttributes fa{};
     hipError_t e = hipErrorInvalidValue;
-#define A2(N) e = hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(&k_step_2d<N>))
+#define A2(N) e = hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(&k_step_2d<N, false>))
     switch (level) {
     case 0: A2(0); break;
     case 1: A2(1); break;

@@ -12,6 +12,10 @@
 //     roles every row, so nothing is copied);
 //   * rows are loaded one at a time (registers go to occupancy rather than to
 //     a prefetched row).
+// With a learned closure (CLOS, level 1) each finished cell also adds dt times
+// the network's correction rates: along x from the cell and its two lane
+// neighbours, along y from the row below (kept in the cell) and
+// the row above.
 // Every face value is computed from the same inputs by the same code whichever
 // wave computes it, so the result does not depend on how a grid is cut into
 // strips and bands.
@@ -34,6 +38,9 @@ struct Cell2 {
     double Fyy[n];        // y-frame normal block (y momenta), gravity included
     double Ft[n];         // tangential block, identical in both frames
     double lx, ly;        // wave-speed bounds along x and y
+    double dn[3];         // closure: (h, qy_0, qy_1) of the row below
+    double crx[2];        // closure: correction rates of (qx_0, qx_1) along x
+    bool inx;             // closure: x features inside the training box
 };
 
 template <int N>
@@ -157,8 +164,8 @@ __device__ __forceinline__ void y_face(const StepArgs &a, const Cell2<N> &P, con
 }
 
 // x-faces of the row of C: face to the right of each lane, neighbour via shuffle.
-template <int N>
-__device__ __forceinline__ void x_faces(const StepArgs &a, const Cell2<N> &C, double *accC)
+template <int N, bool CLOS>
+__device__ __forceinline__ void x_faces(const StepArgs &a, Cell2<N> &C, double *accC, const float *Pl)
 {
     constexpr int n = N + 1;
     constexpr int nf = 2 * n + 1;
@@ -174,6 +181,11 @@ __device__ __forceinline__ void x_faces(const StepArgs &a, const Cell2<N> &C, do
         R.Fa[k] = shfl_dn(X.Fa[k]);
         R.Ft[k] = shfl_dn(X.Ft[k]);
     }
+    if constexpr (CLOS) {
+        const double hm = shfl_up1(X.h), q0m = shfl_up1(X.qa[0]), q1m = shfl_up1(X.qa[1]);
+        C.inx = closure_rate(Pl, a.closure, X.h, X.qa[0], X.qa[1], R.h, R.qa[0], R.qa[1], hm, q0m, q1m, C.crx[0],
+                             C.crx[1]);
+    }
     double Gh[nf], E[nf];
     face_flux<N, true>(X, R, a.g, a.quad, Gh, E);
 #pragma unroll
@@ -185,11 +197,17 @@ __device__ __forceinline__ void x_faces(const StepArgs &a, const Cell2<N> &C, do
 }
 
 // predictor, friction, store, CFL ratio of the new state
-template <int N>
+template <int N, bool CLOS>
 __device__ __forceinline__ double finish_cell(const StepArgs &a, double dt, int64_t cell, bool out,
-                                              const Cell2<N> &c, const double *acc)
+                                              const Cell2<N> &c, const double *acc, const Cell2<N> &above,
+                                              const float *Pl)
 {
     constexpr int n = N + 1;
+    double cry0 = 0.0, cry1 = 0.0;
+    bool iny = true;
+    if constexpr (CLOS)
+        iny = closure_rate(Pl, a.closure, c.h, c.qy[0], c.qy[1], above.h, above.qy[0], above.qy[1], c.dn[0], c.dn[1],
+                           c.dn[2], cry0, cry1);
     const double h = fma(-dt, acc[0], c.h);
     double qx[n], qy[n];
 #pragma unroll
@@ -200,8 +218,17 @@ __device__ __forceinline__ double finish_cell(const StepArgs &a, double dt, int6
     const double ih = rcp(h);
     friction<N>(qx, ih, dt, a.c_slip, a.nu);
     friction<N>(qy, ih, dt, a.c_slip, a.nu);
+    if constexpr (CLOS) {
+        qx[0] = fma(dt, c.crx[0], qx[0]);
+        qx[1] = fma(dt, c.crx[1], qx[1]);
+        qy[0] = fma(dt, cry0, qy[0]);
+        qy[1] = fma(dt, cry1, qy[1]);
+    }
     double r = 0.0;
     if (out) {
+        if constexpr (CLOS) {
+            if (!(c.inx && iny)) atomicAdd(a.oor, 1ull);
+        }
         a.qn[cell] = h;
         double sum = h;
 #pragma unroll
@@ -220,32 +247,38 @@ __device__ __forceinline__ double finish_cell(const StepArgs &a, double dt, int6
 
 // one row: C <- row j (state in `raw`), y-face with P, finish P (row j-1) if
 // requested, x-faces of C.
-template <int N>
+template <int N, bool CLOS>
 __device__ __forceinline__ void row(const StepArgs &a, double dt, Cell2<N> &P, double *accP, Cell2<N> &C,
                                     double *accC, const Raw2<N> &raw, int j, int c, bool outc, bool finish_p,
-                                    double &rmax)
+                                    double &rmax, const float *Pl)
 {
     cell_flux<N>(C, raw, a.g);
+    if constexpr (CLOS) {
+        C.dn[0] = P.h;
+        C.dn[1] = P.qy[0];
+        C.dn[2] = P.qy[1];
+    }
     y_face<N>(a, P, C, accP, accC, finish_p);
-    if (finish_p) rmax = fmax(rmax, finish_cell<N>(a, dt, (int64_t)(j - 1) * a.nx + c, outc, P, accP));
-    x_faces<N>(a, C, accC);
+    if (finish_p)
+        rmax = fmax(rmax, finish_cell<N, CLOS>(a, dt, (int64_t)(j - 1) * a.nx + c, outc, P, accP, C, Pl));
+    x_faces<N, CLOS>(a, C, accC, Pl);
 }
 
 // closing y-face of the band: P is the last row (j1 - 1), raw the row above
-template <int N>
+template <int N, bool CLOS>
 __device__ __forceinline__ void close_band(const StepArgs &a, double dt, Cell2<N> &P, double *accP,
                                            Cell2<N> &G, const Raw2<N> &raw, int j1, int c, bool outc,
-                                           double &rmax)
+                                           double &rmax, const float *Pl)
 {
     cell_flux<N>(G, raw, a.g);
     y_face<N>(a, P, G, accP, nullptr, true);
-    rmax = fmax(rmax, finish_cell<N>(a, dt, (int64_t)(j1 - 1) * a.nx + c, outc, P, accP));
+    rmax = fmax(rmax, finish_cell<N, CLOS>(a, dt, (int64_t)(j1 - 1) * a.nx + c, outc, P, accP, G, Pl));
 }
 
 // Whole band (strip sx, band sy) of one grid: returns the largest CFL ratio
 // of the cells it wrote.  All 64 lanes of the wave must call it.
-template <int N>
-__device__ __forceinline__ double band2d(const StepArgs &a, double dt, int sx, int sy)
+template <int N, bool CLOS = false>
+__device__ __forceinline__ double band2d(const StepArgs &a, double dt, int sx, int sy, const float *Pl = nullptr)
 {
     constexpr int n = N + 1;
     constexpr int nf = 2 * n + 1;
@@ -268,17 +301,17 @@ __device__ __forceinline__ double band2d(const StepArgs &a, double dt, int sx, i
     int j = j0;
     while (true) {
         Raw2<N> cur = nxt;
-        row<N>(a, dt, A, accA, B, accB, cur, j, c, outc, j > j0, rmax);
+        row<N, CLOS>(a, dt, A, accA, B, accB, cur, j, c, outc, j > j0, rmax, Pl);
         load_row<N>(a, j + 1, col, mx, nxt);
         if (++j == j1) {
-            close_band<N>(a, dt, B, accB, A, nxt, j1, c, outc, rmax);
+            close_band<N, CLOS>(a, dt, B, accB, A, nxt, j1, c, outc, rmax, Pl);
             break;
         }
         cur = nxt;
-        row<N>(a, dt, B, accB, A, accA, cur, j, c, outc, true, rmax);
+        row<N, CLOS>(a, dt, B, accB, A, accA, cur, j, c, outc, true, rmax, Pl);
         load_row<N>(a, j + 1, col, mx, nxt);
         if (++j == j1) {
-            close_band<N>(a, dt, A, accA, B, nxt, j1, c, outc, rmax);
+            close_band<N, CLOS>(a, dt, A, accA, B, nxt, j1, c, outc, rmax, Pl);
             break;
         }
     }

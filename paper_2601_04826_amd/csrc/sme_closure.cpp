@@ -1,0 +1,241 @@
+// sme_closure.cpp -- host side of the learned closure (sme_mlp_*, sme_closure_*).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "../../include/sme.h"
+#include "sme_kernels.h"
+
+using namespace sme;
+
+// hooks into the single-grid context (sme_lib.cpp, hidden symbols)
+extern "C" {
+int sme_internal_attach(sme_ctx *c, const ClosureModel *m_host);
+int sme_internal_oor(sme_ctx *c, int64_t *count);
+hipStream_t sme_internal_stream(sme_ctx *c);
+}
+
+struct sme_mlp {
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    ClosureModel host{};       // parameters are mirrored here only on demand
+    float *p = nullptr;        // device parameters [kMlpParams]
+    float *m = nullptr, *v = nullptr, *g = nullptr, *loss = nullptr;
+    float *partial = nullptr, *partial_loss = nullptr;
+    int partial_blocks = 0;
+    int64_t t = 0;             // Adam step count
+    std::string last;
+};
+
+namespace {
+
+int mfail(sme_mlp *m, int code, const char *fmt, ...)
+{
+    if (m) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        m->last = buf;
+    }
+    return code;
+}
+
+#define MCHK(mm, call)                                                                              \
+    do {                                                                                            \
+        hipError_t e_ = (call);                                                                     \
+        if (e_ != hipSuccess) return mfail((mm), SME_EHIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+int ensure_partials(sme_mlp *m, int64_t batch)
+{
+    const int nblk = mlp_grad_blocks(batch);
+    if (nblk <= m->partial_blocks) return SME_OK;
+    (void)hipFree(m->partial);
+    (void)hipFree(m->partial_loss);
+    m->partial = nullptr;
+    m->partial_loss = nullptr;
+    m->partial_blocks = 0;
+    MCHK(m, hipMalloc((void **)&m->partial, (size_t)nblk * kMlpParams * sizeof(float)));
+    MCHK(m, hipMalloc((void **)&m->partial_loss, (size_t)nblk * sizeof(float)));
+    m->partial_blocks = nblk;
+    return SME_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sme_mlp_create(sme_mlp **out, void *stream)
+{
+    if (!out) return SME_EINVAL;
+    *out = nullptr;
+    sme_mlp *m = new (std::nothrow) sme_mlp();
+    if (!m) return SME_ENOMEM;
+    if (stream) {
+        m->stream = (hipStream_t)stream;
+    } else if (hipStreamCreate(&m->stream) == hipSuccess) {
+        m->own_stream = true;
+    } else {
+        delete m;
+        return SME_EHIP;
+    }
+    for (int i = 0; i < kMlpIn; ++i) {
+        m->host.mu[i] = 0.0f;
+        m->host.inv_sigma[i] = 1.0f;
+        m->host.box_lo[i] = -INFINITY;
+        m->host.box_hi[i] = INFINITY;
+    }
+    for (int o = 0; o < kMlpOut; ++o) m->host.out_scale[o] = 1.0f;
+    hipError_t e = hipMalloc((void **)&m->p, kMlpParams * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc((void **)&m->m, kMlpParams * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc((void **)&m->v, kMlpParams * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc((void **)&m->g, kMlpParams * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc((void **)&m->loss, sizeof(float));
+    if (e == hipSuccess) e = hipMemset(m->p, 0, kMlpParams * sizeof(float));
+    if (e == hipSuccess) e = hipMemset(m->m, 0, kMlpParams * sizeof(float));
+    if (e == hipSuccess) e = hipMemset(m->v, 0, kMlpParams * sizeof(float));
+    if (e != hipSuccess) {
+        sme_mlp_destroy(m);
+        return e == hipErrorOutOfMemory ? SME_ENOMEM : SME_EHIP;
+    }
+    *out = m;
+    return SME_OK;
+}
+
+int sme_mlp_set_params(sme_mlp *m, const float *params, int on_device)
+{
+    if (!m || !params) return SME_EINVAL;
+    MCHK(m, hipMemcpyAsync(m->p, params, kMlpParams * sizeof(float),
+                           on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, m->stream));
+    if (!on_device) MCHK(m, hipStreamSynchronize(m->stream));
+    return SME_OK;
+}
+
+int sme_mlp_get_params(sme_mlp *m, float *params, int on_device)
+{
+    if (!m || !params) return SME_EINVAL;
+    MCHK(m, hipMemcpyAsync(params, m->p, kMlpParams * sizeof(float),
+                           on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, m->stream));
+    if (!on_device) MCHK(m, hipStreamSynchronize(m->stream));
+    return SME_OK;
+}
+
+int sme_mlp_set_scaling(sme_mlp *m, const float *mu, const float *sigma, const float *out_scale,
+                        const double *box_lo, const double *box_hi)
+{
+    if (!m) return SME_EINVAL;
+    for (int i = 0; i < kMlpIn; ++i) {
+        if (sigma && !(sigma[i] > 0.0f)) return mfail(m, SME_EINVAL, "sigma must be positive");
+        if (mu) m->host.mu[i] = mu[i];
+        if (sigma) m->host.inv_sigma[i] = 1.0f / sigma[i];
+        if (box_lo) m->host.box_lo[i] = box_lo[i];
+        if (box_hi) m->host.box_hi[i] = box_hi[i];
+    }
+    if (out_scale)
+        for (int o = 0; o < kMlpOut; ++o) m->host.out_scale[o] = out_scale[o];
+    return SME_OK;
+}
+
+int sme_mlp_forward(sme_mlp *m, const float *x, int64_t batch, float *y)
+{
+    if (!m || !x || !y || batch < 0) return SME_EINVAL;
+    MCHK(m, launch_mlp_forward(m->p, x, batch, y, m->stream));
+    return SME_OK;
+}
+
+int sme_mlp_loss_grad(sme_mlp *m, const float *x, const float *t, int64_t batch, float *loss, float *grad)
+{
+    if (!m || !x || !t || batch < 1) return SME_EINVAL;
+    int r = ensure_partials(m, batch);
+    if (r) return r;
+    MCHK(m, launch_mlp_grad(m->p, x, t, batch, m->partial, m->partial_loss, m->g, m->loss, m->stream));
+    if (grad) MCHK(m, hipMemcpyAsync(grad, m->g, kMlpParams * sizeof(float), hipMemcpyDeviceToDevice, m->stream));
+    if (loss) {
+        MCHK(m, hipMemcpyAsync(loss, m->loss, sizeof(float), hipMemcpyDeviceToHost, m->stream));
+        MCHK(m, hipStreamSynchronize(m->stream));
+    }
+    return SME_OK;
+}
+
+int sme_mlp_train_step(sme_mlp *m, const float *x, const float *t, int64_t batch, float lr, float *loss)
+{
+    if (!m || !x || !t || batch < 1 || !(lr > 0)) return SME_EINVAL;
+    int r = ensure_partials(m, batch);
+    if (r) return r;
+    MCHK(m, launch_mlp_grad(m->p, x, t, batch, m->partial, m->partial_loss, m->g, m->loss, m->stream));
+    m->t += 1;
+    const double b1 = 0.9, b2 = 0.999;
+    const float c1 = (float)(1.0 / (1.0 - std::pow(b1, (double)m->t)));
+    const float c2 = (float)(1.0 / (1.0 - std::pow(b2, (double)m->t)));
+    MCHK(m, launch_mlp_adam(m->p, m->g, m->m, m->v, lr, (float)b1, (float)b2, 1e-8f, c1, c2, m->stream));
+    if (loss) {
+        MCHK(m, hipMemcpyAsync(loss, m->loss, sizeof(float), hipMemcpyDeviceToHost, m->stream));
+        MCHK(m, hipStreamSynchronize(m->stream));
+    }
+    return SME_OK;
+}
+
+int sme_mlp_reset_optimizer(sme_mlp *m)
+{
+    if (!m) return SME_EINVAL;
+    m->t = 0;
+    MCHK(m, hipMemsetAsync(m->m, 0, kMlpParams * sizeof(float), m->stream));
+    MCHK(m, hipMemsetAsync(m->v, 0, kMlpParams * sizeof(float), m->stream));
+    return SME_OK;
+}
+
+const char *sme_mlp_last_error(const sme_mlp *m) { return m ? m->last.c_str() : "no network"; }
+
+void sme_mlp_destroy(sme_mlp *m)
+{
+    if (!m) return;
+    if (m->stream) (void)hipStreamSynchronize(m->stream);
+    (void)hipFree(m->p);
+    (void)hipFree(m->m);
+    (void)hipFree(m->v);
+    (void)hipFree(m->g);
+    (void)hipFree(m->loss);
+    (void)hipFree(m->partial);
+    (void)hipFree(m->partial_loss);
+    if (m->own_stream) (void)hipStreamDestroy(m->stream);
+    delete m;
+}
+
+int sme_closure_samples(const double *q8, int64_t stride8, const double *q8_next, int64_t stride8n,
+                        const double *q1_step, int64_t stride1, int64_t ncells, double dt, const int64_t *cells,
+                        int64_t nsamples, float *feat, float *targ, void *stream)
+{
+    if (!q8 || !q8_next || !q1_step || !cells || !feat || !targ || ncells < 3 || nsamples < 0 || !(dt > 0))
+        return SME_EINVAL;
+    if (stride8 < ncells || stride8n < ncells || stride1 < ncells) return SME_EINVAL;
+    hipError_t e = launch_closure_samples(q8, stride8, q8_next, stride8n, q1_step, stride1, ncells, dt, cells, nsamples,
+                                          feat, targ, (hipStream_t)stream);
+    return e == hipSuccess ? SME_OK : SME_EHIP;
+}
+
+int sme_closure_attach(sme_ctx *ctx, const sme_mlp *m)
+{
+    if (!ctx) return SME_EINVAL;
+    if (!m) return sme_internal_attach(ctx, nullptr);
+    ClosureModel cm = m->host;
+    // the parameters come from the device copy
+    sme_mlp *mm = const_cast<sme_mlp *>(m);
+    MCHK(mm, hipMemcpyAsync(cm.params, m->p, kMlpParams * sizeof(float), hipMemcpyDeviceToHost, m->stream));
+    MCHK(mm, hipStreamSynchronize(m->stream));
+    return sme_internal_attach(ctx, &cm);
+}
+
+int sme_closure_out_of_range(sme_ctx *ctx, int64_t *cells)
+{
+    if (!ctx || !cells) return SME_EINVAL;
+    return sme_internal_oor(ctx, cells);
+}
+
+}  // extern "C"

@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include "sme_device.h"
+#include "sme_mlp.h"
 
 namespace sme {
 
@@ -53,6 +54,9 @@ struct StepArgs {
     Slot *slots;
     int sa, sb, sc;
     ErrWord *err;
+    // learned closure (level 1 only; null = plain step)
+    const ClosureModel *closure;
+    unsigned long long *oor;  // cells whose features left the training range
 };
 
 // ---------------------------------------------------------------------------
@@ -97,6 +101,16 @@ int step_2d_vgprs(int level);  // registers per lane of the structured step kern
 hipError_t launch_step_tri(int level, const StepArgs &a, hipStream_t s);
 hipError_t launch_eig(int dim, int kind, int level, const StepArgs &a, hipStream_t s);
 hipError_t launch_slots_reset(Slot *slots, ErrWord *err, int sa, hipStream_t s);  // err may be null
+// closure network training and samples (k_mlp.hip)
+hipError_t launch_mlp_forward(const float *params, const float *x, int64_t B, float *y, hipStream_t s);
+int mlp_grad_blocks(int64_t B);
+hipError_t launch_mlp_grad(const float *params, const float *x, const float *t, int64_t B, float *partial,
+                           float *partial_loss, float *grad, float *loss, hipStream_t s);
+hipError_t launch_mlp_adam(float *p, const float *g, float *m, float *v, float lr, float b1, float b2, float eps,
+                           float c1, float c2, hipStream_t s);
+hipError_t launch_closure_samples(const double *q8, int64_t s8, const double *q8n, int64_t s8n, const double *q1,
+                                  int64_t s1, int64_t n, double dt, const int64_t *cells, int64_t ns, float *feat,
+                                  float *targ, hipStream_t s);
 hipError_t launch_permute(const double *src, int64_t sstride, double *dst, int64_t dstride,
                           const int64_t *map, int64_t ncells, int nf, hipStream_t s);
 

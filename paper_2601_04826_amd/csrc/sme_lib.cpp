@@ -58,6 +58,8 @@ struct sme_ctx {
     Slot *slots = nullptr;
     ErrWord *err = nullptr;
     double *quad_dev = nullptr;      // Gauss points [kMaxQuad] then weights [kMaxQuad]
+    ClosureModel *closure = nullptr;  // learned closure attached to a level-1 context
+    unsigned long long *oor = nullptr;  // cells that left the closure's training range
     int cur = 0;   // which q[] holds the state
     int sa = 0;    // slot describing the current state
     bool has_state = false;
@@ -315,6 +317,8 @@ StepArgs make_args(const sme_ctx *c)
     a.sb = (c->sa + 1) % 3;
     a.sc = (c->sa + 2) % 3;
     a.err = c->err;
+    a.closure = c->closure;
+    a.oor = c->oor;
     return a;
 }
 
@@ -567,6 +571,7 @@ int sme_set_state(sme_ctx *c, const double *q, int on_device)
     }
     // fresh clock and CFL ratio of the loaded state
     c->sa = 0;
+    if (c->oor) HIPCHK(c, hipMemsetAsync(c->oor, 0, sizeof(unsigned long long), c->stream));
     HIPCHK(c, launch_slots_reset(c->slots, c->err, 0, c->stream));
     StepArgs a = make_args(c);
     HIPCHK(c, launch_eig(c->kind == SME_MESH_1D ? 1 : 2, c->kind, c->level, a, c->stream));
@@ -686,6 +691,45 @@ int sme_basis_tensors(int level, double *M, double *A, double *B, double *K)
     }
 }
 
+// ---- hooks for the closure front end (sme_closure.cpp) ----
+__attribute__((visibility("hidden"))) int sme_internal_attach(sme_ctx *c, const ClosureModel *m_host)
+{
+    if (!c) return SME_EINVAL;
+    if (!m_host) {
+        (void)hipFree(c->closure);
+        c->closure = nullptr;
+        drop_graphs(c);
+        return SME_OK;
+    }
+    if (c->level != 1 || c->kind == SME_MESH_2D_TRI)
+        return fail(c, SME_EINVAL, "the learned closure acts on level-1 1D and structured 2D grids");
+    if (!c->closure) {
+        if (dalloc(c, &c->closure, 1)) return SME_ENOMEM;
+    }
+    if (!c->oor) {
+        if (dalloc(c, &c->oor, 1)) return SME_ENOMEM;
+        HIPCHK(c, hipMemset(c->oor, 0, sizeof(unsigned long long)));
+    }
+    HIPCHK(c, hipMemcpyAsync(c->closure, m_host, sizeof(ClosureModel), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    drop_graphs(c);
+    return SME_OK;
+}
+
+__attribute__((visibility("hidden"))) int sme_internal_oor(sme_ctx *c, int64_t *count)
+{
+    if (!c) return SME_EINVAL;
+    unsigned long long v = 0;
+    if (c->oor) {
+        HIPCHK(c, hipMemcpyAsync(&v, c->oor, sizeof v, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    *count = (int64_t)v;
+    return SME_OK;
+}
+
+__attribute__((visibility("hidden"))) hipStream_t sme_internal_stream(sme_ctx *c) { return c ? c->stream : nullptr; }
+
 const char *sme_strerror(int code)
 {
     switch (code) {
@@ -718,6 +762,8 @@ void sme_destroy(sme_ctx *c)
     (void)hipFree(c->slots);
     (void)hipFree(c->err);
     (void)hipFree(c->quad_dev);
+    (void)hipFree(c->closure);
+    (void)hipFree(c->oor);
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }

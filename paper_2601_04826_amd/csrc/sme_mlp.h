@@ -1,0 +1,95 @@
+// sme_mlp.h -- the closure network (9 -> 64 -> 64 -> 2, tanh, FP32), device side.
+//
+// The learned closure maps per-cell features of a level-1 state to correction
+// rates of its momentum moments (q_0, q_1), so that level 1 stands in for
+// level 8.  Parameters are one flat FP32 array:
+//   W1[64][9], b1[64], W2[64][64], b2[64], W3[2][64], b3[2]   (4,930 floats)
+// The network works on normalised inputs x~ = (x - mu) / sigma and outputs
+// normalised rates y~; the rate is y = y~ * s_out.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace sme {
+
+constexpr int kMlpIn = 9, kMlpHid = 64, kMlpOut = 2;
+constexpr int kOffW1 = 0;
+constexpr int kOffB1 = kOffW1 + kMlpHid * kMlpIn;
+constexpr int kOffW2 = kOffB1 + kMlpHid;
+constexpr int kOffB2 = kOffW2 + kMlpHid * kMlpHid;
+constexpr int kOffW3 = kOffB2 + kMlpHid;
+constexpr int kOffB3 = kOffW3 + kMlpOut * kMlpHid;
+constexpr int kMlpParams = kOffB3 + kMlpOut;  // 4930
+
+// Everything the fused level-1 step needs besides the parameters.
+struct ClosureModel {
+    float params[kMlpParams];
+    float mu[kMlpIn];
+    float inv_sigma[kMlpIn];
+    float out_scale[kMlpOut];
+    double box_lo[kMlpIn];  // training range of the raw features (fallback test)
+    double box_hi[kMlpIn];
+};
+
+// copy the parameters of a model into LDS (all threads of the block call it)
+__device__ __forceinline__ void mlp_stage(const float *__restrict__ g, float *s)
+{
+    for (int k = threadIdx.x; k < kMlpParams; k += blockDim.x) s[k] = g[k];
+    __syncthreads();
+}
+
+// forward pass of one sample; P = parameters (LDS), x = normalised inputs
+__device__ __forceinline__ void mlp_forward(const float *P, const float *x, float *a1, float *a2, float *y)
+{
+#pragma unroll
+    for (int j = 0; j < kMlpHid; ++j) {
+        float z = P[kOffB1 + j];
+#pragma unroll
+        for (int i = 0; i < kMlpIn; ++i) z = fmaf(P[kOffW1 + j * kMlpIn + i], x[i], z);
+        a1[j] = tanhf(z);
+    }
+#pragma unroll
+    for (int j = 0; j < kMlpHid; ++j) {
+        float z = P[kOffB2 + j];
+#pragma unroll
+        for (int i = 0; i < kMlpHid; ++i) z = fmaf(P[kOffW2 + j * kMlpHid + i], a1[i], z);
+        a2[j] = tanhf(z);
+    }
+#pragma unroll
+    for (int o = 0; o < kMlpOut; ++o) {
+        float z = P[kOffB3 + o];
+#pragma unroll
+        for (int i = 0; i < kMlpHid; ++i) z = fmaf(P[kOffW3 + o * kMlpHid + i], a2[i], z);
+        y[o] = z;
+    }
+}
+
+}  // namespace sme
+
+namespace sme {
+
+// Closure correction rates of the two normal momentum moments of one cell
+// along one direction.  Features: the cell's (h, q_0, q_1), its differences to
+// the neighbour ahead (p) and behind (m) along the direction.  P = parameters
+// in LDS, M = the model (normalisation, output scale, training box).
+// Returns false if a feature lies outside the training box.
+__device__ __forceinline__ bool closure_rate(const float *P, const ClosureModel *M, double h, double q0, double q1,
+                                             double hp, double q0p, double q1p, double hm, double q0m, double q1m,
+                                             double &r0, double &r1)
+{
+    const double f[kMlpIn] = {h, q0, q1, hp - h, q0p - q0, q1p - q1, h - hm, q0 - q0m, q1 - q1m};
+    float x[kMlpIn];
+    bool inside = true;
+#pragma unroll
+    for (int i = 0; i < kMlpIn; ++i) {
+        inside &= (f[i] >= M->box_lo[i]) & (f[i] <= M->box_hi[i]);
+        x[i] = ((float)f[i] - M->mu[i]) * M->inv_sigma[i];
+    }
+    float a1[kMlpHid], a2[kMlpHid], y[kMlpOut];
+    mlp_forward(P, x, a1, a2, y);
+    r0 = (double)(y[0] * M->out_scale[0]);
+    r1 = (double)(y[1] * M->out_scale[1]);
+    return inside;
+}
+
+}  // namespace sme

@@ -32,6 +32,9 @@ EXPORTS = [
     "sme_batch_init", "sme_batch_set_state", "sme_batch_get_state", "sme_batch_run", "sme_batch_time",
     "sme_batch_cells", "sme_batch_rows", "sme_batch_set_rows", "sme_batch_autotune",
     "sme_batch_last_error", "sme_batch_destroy",
+    "sme_mlp_create", "sme_mlp_set_params", "sme_mlp_get_params", "sme_mlp_set_scaling", "sme_mlp_forward",
+    "sme_mlp_loss_grad", "sme_mlp_train_step", "sme_mlp_reset_optimizer", "sme_mlp_last_error", "sme_mlp_destroy",
+    "sme_closure_samples", "sme_closure_attach", "sme_closure_out_of_range",
 ]
 
 
@@ -89,6 +92,19 @@ def _load():
         "sme_batch_autotune": (i, [vp, ctypes.c_char_p]),
         "sme_batch_last_error": (ctypes.c_char_p, [vp]),
         "sme_batch_destroy": (None, [vp]),
+        "sme_mlp_create": (i, [P(vp), vp]),
+        "sme_mlp_set_params": (i, [vp, vp, i]),
+        "sme_mlp_get_params": (i, [vp, vp, i]),
+        "sme_mlp_set_scaling": (i, [vp, vp, vp, vp, vp, vp]),
+        "sme_mlp_forward": (i, [vp, vp, i64, vp]),
+        "sme_mlp_loss_grad": (i, [vp, vp, vp, i64, vp, vp]),
+        "sme_mlp_train_step": (i, [vp, vp, vp, i64, ctypes.c_float, vp]),
+        "sme_mlp_reset_optimizer": (i, [vp]),
+        "sme_mlp_last_error": (ctypes.c_char_p, [vp]),
+        "sme_mlp_destroy": (None, [vp]),
+        "sme_closure_samples": (i, [vp, i64, vp, i64, vp, i64, i64, d, vp, i64, vp, vp, vp]),
+        "sme_closure_attach": (i, [vp, vp]),
+        "sme_closure_out_of_range": (i, [vp, P(i64)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -262,6 +278,19 @@ class Solver:
     def time(self):
         return sme_time(self.ctx)
 
+    def attach_closure(self, mlp):
+        """Attach a trained network (an MLP); None detaches."""
+        _check(_lib.sme_closure_attach(self.ctx, mlp.ctx if mlp is not None else None), self.ctx)
+
+    def out_of_range(self):
+        n = ctypes.c_int64()
+        _check(_lib.sme_closure_out_of_range(self.ctx, ctypes.byref(n)), self.ctx)
+        return n.value
+
+    def state_device(self):
+        """(pointer, field stride) of the current state in the internal order."""
+        return _lib.sme_state_device(self.ctx), _lib.sme_field_stride(self.ctx)
+
     def close(self):
         if self.ctx:
             sme_destroy(self.ctx)
@@ -347,3 +376,100 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+NPARAM = 4930
+
+
+def _mcheck(code, m):
+    if code != SME_OK:
+        msg = _lib.sme_strerror(code).decode()
+        detail = _lib.sme_mlp_last_error(m).decode() if m else ""
+        raise SmeError(code, f"{msg}: {detail}" if detail else msg)
+
+
+def _fptr(a, dtype=np.float32):
+    """(pointer, keepalive) of a torch CUDA tensor or a host numpy array."""
+    if isinstance(a, torch.Tensor):
+        return ctypes.c_void_p(a.data_ptr()), a
+    a = np.ascontiguousarray(a, dtype=dtype)
+    return a.ctypes.data_as(ctypes.c_void_p), a
+
+
+class MLP:
+    """The closure network (9 -> 64 -> 64 -> 2, tanh, FP32) on the device."""
+
+    def __init__(self, params=None, stream=None):
+        if stream is None and torch.cuda.is_available():
+            stream = torch.cuda.current_stream().cuda_stream
+        self.ctx = ctypes.c_void_p()
+        _mcheck(_lib.sme_mlp_create(ctypes.byref(self.ctx), ctypes.c_void_p(stream or 0)), None)
+        if params is not None:
+            self.set_params(params)
+
+    def set_params(self, params):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        assert p.size == NPARAM
+        _mcheck(_lib.sme_mlp_set_params(self.ctx, p.ctypes.data_as(ctypes.c_void_p), 0), self.ctx)
+
+    def get_params(self):
+        p = np.empty(NPARAM, dtype=np.float32)
+        _mcheck(_lib.sme_mlp_get_params(self.ctx, p.ctypes.data_as(ctypes.c_void_p), 0), self.ctx)
+        return p
+
+    def set_scaling(self, mu, sigma, out_scale, box_lo, box_hi):
+        a = [np.ascontiguousarray(v, dtype=np.float32) for v in (mu, sigma, out_scale)]
+        b = [np.ascontiguousarray(v, dtype=np.float64) for v in (box_lo, box_hi)]
+        _mcheck(_lib.sme_mlp_set_scaling(self.ctx, *(x.ctypes.data_as(ctypes.c_void_p) for x in a + b)), self.ctx)
+
+    def forward(self, x):
+        """x: torch CUDA float32 [B, 9] (normalised) -> [B, 2]."""
+        y = torch.empty((x.shape[0], 2), dtype=torch.float32, device=x.device)
+        _mcheck(_lib.sme_mlp_forward(self.ctx, ctypes.c_void_p(x.data_ptr()), x.shape[0],
+                                     ctypes.c_void_p(y.data_ptr())), self.ctx)
+        return y
+
+    def loss_grad(self, x, t):
+        g = torch.empty(NPARAM, dtype=torch.float32, device=x.device)
+        loss = ctypes.c_float()
+        _mcheck(_lib.sme_mlp_loss_grad(self.ctx, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(t.data_ptr()),
+                                       x.shape[0], ctypes.byref(loss), ctypes.c_void_p(g.data_ptr())), self.ctx)
+        return loss.value, g
+
+    def train_step(self, x, t, lr, want_loss=False):
+        loss = ctypes.c_float()
+        _mcheck(_lib.sme_mlp_train_step(self.ctx, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(t.data_ptr()),
+                                        x.shape[0], ctypes.c_float(lr),
+                                        ctypes.byref(loss) if want_loss else None), self.ctx)
+        return loss.value if want_loss else None
+
+    def reset_optimizer(self):
+        _mcheck(_lib.sme_mlp_reset_optimizer(self.ctx), self.ctx)
+
+    def close(self):
+        if self.ctx:
+            _lib.sme_mlp_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def closure_samples(q8, q8_next, q1_step, dt, cells, stream=None):
+    """Training samples (features [S, 9], targets [S, 2], FP32 torch CUDA) from
+    torch CUDA float64 states [nf, n] of a periodic 1D row."""
+    n = q8.shape[1]
+    ns = cells.shape[0]
+    feat = torch.empty((ns, 9), dtype=torch.float32, device=q8.device)
+    targ = torch.empty((ns, 2), dtype=torch.float32, device=q8.device)
+    if stream is None:
+        stream = torch.cuda.current_stream().cuda_stream
+    code = _lib.sme_closure_samples(ctypes.c_void_p(q8.data_ptr()), q8.stride(0), ctypes.c_void_p(q8_next.data_ptr()),
+                                    q8_next.stride(0), ctypes.c_void_p(q1_step.data_ptr()), q1_step.stride(0), n,
+                                    float(dt), ctypes.c_void_p(cells.data_ptr()), ns, ctypes.c_void_p(feat.data_ptr()),
+                                    ctypes.c_void_p(targ.data_ptr()), ctypes.c_void_p(stream or 0))
+    _check(code)
+    return feat, targ

@@ -1,0 +1,253 @@
+"""GPU tests of the learned closure: the FP32 network kernels against the FP64
+oracle network (forward, gradient, Adam), the training samples against the
+oracle's level-1 step, the fused level-1 + closure step against the oracle,
+the zero network reducing to plain level 1 bitwise, the out-of-range flag,
+and the gain of a trained closure on held-out seeds."""
+import numpy as np
+import pytest
+
+from oracle import mlp as omlp
+from oracle import sme as orc
+from paper_2601_04826_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2601_04826_amd import closure, sme
+
+    return torch, sme, closure
+
+
+def rand_params(seed, scale=1.0):
+    rng = np.random.default_rng(seed)
+    return (omlp.init_params(seed) * scale + 0.02 * rng.standard_normal(omlp.NPARAM)).astype(np.float32)
+
+
+def test_forward_matches_oracle(env):
+    torch, sme, _ = env
+    p = rand_params(1)
+    x = np.random.default_rng(2).standard_normal((1000, 9)).astype(np.float32)
+    m = sme.MLP(p)
+    y = m.forward(torch.from_numpy(x).cuda()).cpu().numpy()
+    ref, _ = omlp.forward(p.astype(np.float64), x.astype(np.float64))
+    np.testing.assert_allclose(y, ref, rtol=0, atol=2e-5 * max(1.0, np.abs(ref).max()))
+    m.close()
+
+
+@pytest.mark.parametrize("B", [64, 300])
+def test_gradient_matches_oracle(env, B):
+    torch, sme, _ = env
+    p = rand_params(3)
+    rng = np.random.default_rng(B)
+    x = rng.standard_normal((B, 9)).astype(np.float32)
+    t = rng.standard_normal((B, 2)).astype(np.float32)
+    m = sme.MLP(p)
+    loss, g = m.loss_grad(torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda())
+    g = g.cpu().numpy()
+    lref, gref = omlp.loss_grad(p.astype(np.float64), x.astype(np.float64), t.astype(np.float64))
+    assert loss == pytest.approx(lref, rel=1e-5)
+    assert np.max(np.abs(g - gref)) <= 1e-4 * np.max(np.abs(gref))
+    m.close()
+
+
+def test_adam_step_matches_oracle(env):
+    torch, sme, _ = env
+    p = rand_params(5)
+    rng = np.random.default_rng(6)
+    x = rng.standard_normal((256, 9)).astype(np.float32)
+    t = rng.standard_normal((256, 2)).astype(np.float32)
+    m = sme.MLP(p)
+    lr = 1e-3
+    xd, td = torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda()
+    m.train_step(xd, td, lr)
+    m.train_step(xd, td, lr)
+    got = m.get_params().astype(np.float64)
+    pp, mm, vv = p.astype(np.float64), np.zeros(omlp.NPARAM), np.zeros(omlp.NPARAM)
+    for step in (1, 2):
+        _, g = omlp.loss_grad(pp, x.astype(np.float64), t.astype(np.float64))
+        pp, mm, vv = omlp.adam(pp, g, mm, vv, step, lr)
+    _, g0 = omlp.loss_grad(p.astype(np.float64), x.astype(np.float64), t.astype(np.float64))
+    big = np.abs(g0) > 1e-3 * np.abs(g0).max()
+    assert np.max(np.abs(got - pp)[big]) <= 2e-2 * lr
+    m.close()
+
+
+def test_samples_match_oracle(env):
+    torch, sme, _ = env
+    p8 = W.smooth_1d(n=512, level=8, seed=1001, steps=30)
+    s8 = sme.Solver(p8)
+    s8.set_state(p8["q"])
+    s8.run(30)
+    q8 = s8.get_state()
+    dt = s8.step(0.0, sync=True)
+    q8n = s8.get_state()
+    s8.close()
+    p1 = dict(p8, level=1, q=q8[:3].copy())
+    q1_orc, _ = orc.from_problem(p1).step(q8[:3].copy(), dt)
+    cells = torch.arange(512, device="cuda")
+    # GPU level-1 step from the same state
+    s1 = sme.Solver(p1)
+    s1.set_state(q8[:3].copy())
+    s1.step(dt)
+    q1 = s1.get_state()
+    s1.close()
+    f, t = sme.closure_samples(torch.from_numpy(q8).cuda(), torch.from_numpy(q8n).cuda(), torch.from_numpy(q1).cuda(),
+                               dt, cells)
+    torch.cuda.synchronize()
+    f, t = f.cpu().numpy(), t.cpu().numpy()
+    fo = omlp.features_1d(q8[0], q8[1], q8[2])
+    to = omlp.closure_target(q8, q8n, q1_orc, dt)
+    np.testing.assert_allclose(f, fo.astype(np.float32), rtol=1e-6, atol=1e-7)
+    np.testing.assert_allclose(t, to, rtol=1e-5, atol=1e-5 * np.abs(to).max())
+
+
+def scaled_mlp(sme, p, seed=0):
+    m = sme.MLP(p)
+    rng = np.random.default_rng(seed)
+    mu = rng.uniform(-0.1, 0.1, 9).astype(np.float32)
+    sig = rng.uniform(0.5, 2.0, 9).astype(np.float32)
+    osc = np.array([0.3, 0.7], dtype=np.float32)
+    m.set_scaling(mu, sig, osc, np.full(9, -1e3), np.full(9, 1e3))
+    return m, mu, sig, osc
+
+
+def oracle_rate(p, mu, sig, osc, feat):
+    x = ((feat.astype(np.float32) - mu) * (np.float32(1.0) / sig)).astype(np.float64)
+    y, _ = omlp.forward(p.astype(np.float64), x)
+    return y * osc.astype(np.float64)
+
+
+def test_closure_step_1d_matches_oracle(env):
+    torch, sme, _ = env
+    p = rand_params(7, scale=0.3)
+    m, mu, sig, osc = scaled_mlp(sme, p)
+    prob = W.smooth_1d(n=300, level=1, seed=1003)
+    s = sme.Solver(prob)
+    s.attach_closure(m)
+    s.set_state(prob["q"])
+    dt = 2e-3
+    s.step(dt)
+    got = s.get_state()
+    s.close()
+    ref, _ = orc.from_problem(prob).step(prob["q"], dt)
+    q = prob["q"]
+    r = oracle_rate(p, mu, sig, osc, omlp.features_1d(q[0], q[1], q[2]))
+    ref[1] += dt * r[:, 0]
+    ref[2] += dt * r[:, 1]
+    np.testing.assert_allclose(got, ref, rtol=0, atol=5e-9 * np.abs(ref).max())
+    m.close()
+
+
+def test_closure_step_2d_matches_oracle(env):
+    torch, sme, _ = env
+    p = rand_params(8, scale=0.3)
+    m, mu, sig, osc = scaled_mlp(sme, p, seed=1)
+    n = 70
+    prob = W.struct_2d(n=n, level=1, L=7.0)
+    rng = np.random.default_rng(4)
+    prob["q"][1:] = prob["q"][0] * rng.uniform(-0.3, 0.3, size=prob["q"][1:].shape)
+    s = sme.Solver(prob)
+    s.attach_closure(m)
+    s.set_state(prob["q"])
+    dt = 1e-3
+    s.step(dt)
+    got = s.get_state()
+    s.close()
+    ref, _ = orc.from_problem(prob).step(prob["q"], dt)
+    q = prob["q"].reshape(5, n, n)  # [f, j, i], periodic
+
+    def feats(h, a, b, axis):
+        hp, ap, bp = (np.roll(v, -1, axis=axis) for v in (h, a, b))
+        hm, am, bm = (np.roll(v, 1, axis=axis) for v in (h, a, b))
+        return np.stack([h, a, b, hp - h, ap - a, bp - b, h - hm, a - am, b - bm], axis=-1).reshape(-1, 9)
+
+    rx = oracle_rate(p, mu, sig, osc, feats(q[0], q[1], q[2], axis=1))
+    ry = oracle_rate(p, mu, sig, osc, feats(q[0], q[3], q[4], axis=0))
+    ref[1] += dt * rx[:, 0]
+    ref[2] += dt * rx[:, 1]
+    ref[3] += dt * ry[:, 0]
+    ref[4] += dt * ry[:, 1]
+    np.testing.assert_allclose(got, ref, rtol=0, atol=5e-9 * np.abs(ref).max())
+    m.close()
+
+
+@pytest.mark.parametrize("kind", ["1d", "2d"])
+def test_zero_network_is_plain_level1(env, kind):
+    torch, sme, _ = env
+    prob = W.smooth_1d(n=500, level=1, seed=1010) if kind == "1d" else W.struct_2d(n=90, level=1)
+    out = []
+    for attach in (False, True):
+        s = sme.Solver(prob)
+        if attach:
+            m = sme.MLP(np.zeros(omlp.NPARAM, dtype=np.float32))
+            s.attach_closure(m)
+        s.set_state(prob["q"])
+        s.run(40)
+        out.append(s.get_state())
+        s.close()
+    assert np.array_equal(out[0], out[1])
+
+
+def test_out_of_range_flag(env):
+    torch, sme, _ = env
+    m = sme.MLP(np.zeros(omlp.NPARAM, dtype=np.float32))
+    prob = W.smooth_1d(n=256, level=1, seed=1011)
+    # a box that excludes depths above 1.0 m
+    lo = np.full(9, -1e3)
+    hi = np.full(9, 1e3)
+    hi[0] = 1.0
+    m.set_scaling(np.zeros(9), np.ones(9), np.ones(2), lo, hi)
+    s = sme.Solver(prob)
+    s.attach_closure(m)
+    s.set_state(prob["q"])
+    s.run(3)
+    assert s.out_of_range() > 0
+    hi[0] = 1e3
+    m.set_scaling(np.zeros(9), np.ones(9), np.ones(2), lo, hi)
+    s.attach_closure(m)
+    s.set_state(prob["q"])
+    s.run(3)
+    assert s.out_of_range() == 0
+    s.close()
+
+
+def test_trained_closure_gain_on_held_out_seeds(env):
+    """Train on level-8 runs the solver generates (seeds 1000..1023), then on
+    held-out seeds compare level 1 + closure and plain level 1 against level 8
+    at the same time: the closure must cut the relative L1 error of (h, hu)."""
+    torch, sme, closure = env
+    feat, targ = closure.generate(range(1000, 1024), n=1024, steps=600, every=3, cells_per_snapshot=256)
+    print("samples", feat.shape[0], flush=True)
+    mlp, sc, hist = closure.fit(feat, targ, epochs=12, batch=4096, lr=3e-3, lr_end=1e-4, seed=0)
+    assert hist[-1] < hist[0]
+    gains = []
+    for seed in (1256, 1257, 1258):
+        p8 = W.smooth_1d(n=1024, level=8, seed=seed)
+        T = 0.5
+        s8 = sme.Solver(p8)
+        s8.set_state(p8["q"])
+        s8.run(10 ** 6, t_end=T)
+        ref = s8.get_state()
+        s8.close()
+        res = {}
+        for name, net in (("plain", sme.MLP(np.zeros(omlp.NPARAM, dtype=np.float32))), ("closure", mlp)):
+            p1 = dict(p8, level=1, q=p8["q"][:3].copy())
+            s1 = sme.Solver(p1)
+            s1.attach_closure(net)
+            s1.set_state(p1["q"])
+            s1.run(10 ** 6, t_end=T)
+            q1 = s1.get_state()
+            assert s1.out_of_range() >= 0
+            s1.close()
+            e = closure.relative_l1(q1, ref[:3], fields=(0, 1))
+            res[name] = e
+        g = (res["closure"][0] + res["closure"][1]) / (res["plain"][0] + res["plain"][1])
+        print(f"seed {seed}: plain {res['plain']} closure {res['closure']} gain {g:.3f}", flush=True)
+        gains.append(g)
+    assert np.mean(gains) < 1.0
