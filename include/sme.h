@@ -123,8 +123,9 @@ int sme_eigmax(sme_ctx *ctx, double *lam_max, double *dt);
 int sme_step(sme_ctx *ctx, double dt, double *dt_used);
 
 /* n_steps CFL steps, queued as replays of a captured HIP graph.  t_end > 0
- * stops the simulated time at t_end (the last step is shortened, later steps
- * are no-ops).  If t_out / steps_done are not NULL the stream is synchronised
+ * stops the simulated time at t_end: the last step is shortened, and the call
+ * stops queueing steps once the device clock has reached t_end (it looks every
+ * 60 steps, so up to 60 steps after that are no-ops).  If t_out / steps_done are not NULL the stream is synchronised
  * and the simulated time since sme_set_state and the number of steps that
  * advanced the state are returned; SME_ENONPHYS is returned if a step produced
  * h <= 0 or a non-finite value (the state is then not usable). */

@@ -636,12 +636,25 @@ int sme_run(sme_ctx *c, int64_t n_steps, double t_end, double *t_out, int64_t *s
     const double te = t_end > 0 ? t_end : 0.0;
     int64_t left = n_steps;
     const bool use_graphs = getenv("SME_NO_GRAPH") == nullptr;
+    // with an end time, look at the device clock every kCheckChunks graphs and
+    // stop once it has reached t_end (the steps after that would be no-ops)
+    constexpr int kCheckChunks = 10;
+    int chunks = 0;
     while (use_graphs && left >= kGraphSteps) {
         hipGraphExec_t ex;
         int r = get_graph(c, te, &ex);
         if (r) return r;
         HIPCHK(c, hipGraphLaunch(ex, c->stream));
         left -= kGraphSteps;  // after six steps cur and slot are back where they started
+        if (te > 0.0 && ++chunks % kCheckChunks == 0) {
+            Slot s;
+            int rr = read_slot(c, &s, nullptr);
+            if (rr) return rr;
+            if (s.t >= te) {
+                left = 0;
+                break;
+            }
+        }
     }
     while (left-- > 0) HIPCHK(c, launch_one_step(c, 0.0, te));
     if (t_out || steps_done) {
