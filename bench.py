@@ -44,6 +44,8 @@ WORKLOADS = {
                               name="struct_2d_4096x4096_level2_periodic"),
     "batch_512": dict(gen="batch", args={}, kernel="k_batch_step",
                       name="batch_512_grids_side64-512_levels1-4_walls"),
+    "closure_2048": dict(gen="closure", args={}, kernel="k_step_2d<1,closure>",
+                         name="closure_level1_vs_level8_2048x2048_periodic"),
 }
 
 
@@ -96,6 +98,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-tune", action="store_true", help="batch: skip the tile autotuner")
+    ap.add_argument("--closure-seeds", type=int, default=64, help="closure: level-8 training runs")
+    ap.add_argument("--closure-steps", type=int, default=1000, help="closure: steps per training run")
+    ap.add_argument("--closure-epochs", type=int, default=15)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (read + write), 5 times: "
                          "calibrates the HBM byte counters against a kernel of known traffic")
@@ -126,6 +131,8 @@ def main():
     wl = WORKLOADS[args.workload]
     if wl["gen"] == "batch":
         return bench_batch(args, wl, torch, sme, workloads)
+    if wl["gen"] == "closure":
+        return bench_closure(args, wl, torch, sme, workloads)
     t0 = time.perf_counter()
     problem = getattr(workloads, wl["gen"])(**wl["args"])
     print(f"[bench] workload {wl['name']}: {problem['ncells']} cells, level {problem['level']} "
@@ -194,6 +201,99 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(problem, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+def bench_closure(args, wl, torch, sme, workloads):
+    """Learned closure: train on level-8 runs the solver generates, then run
+    level 1 + closure and plain level 8 (and plain level 1) on a 2048^2 periodic
+    2D grid to the same time; report both throughputs, the speedup at the same
+    simulated time and the relative L1 errors of (h, hu) against level 8."""
+    from paper_2601_04826_amd import closure
+
+    st = torch.cuda.Stream()
+    t0 = time.perf_counter()
+    # trained at the evaluation grid spacing (2048 cells on [0, 10] m): the
+    # features hold neighbour differences, which scale with the spacing
+    feat, targ = closure.generate(range(1000, 1000 + args.closure_seeds), n=2048, steps=args.closure_steps,
+                                  every=5, cells_per_snapshot=256, stream=st)
+    t1 = time.perf_counter()
+    mlp, sc, hist = closure.fit(feat, targ, epochs=args.closure_epochs, batch=4096, lr=3e-3, lr_end=1e-4,
+                                stream=st)
+    t2 = time.perf_counter()
+    print(f"[bench] closure data: {feat.shape[0]} samples from {args.closure_seeds} level-8 runs in {t1 - t0:.1f} s; "
+          f"training {args.closure_epochs} epochs in {t2 - t1:.1f} s (loss {hist[0]:.4f} -> {hist[-1]:.4f})",
+          file=sys.stderr, flush=True)
+    p8 = workloads.smooth_2d(n=2048, level=8, seed=2000)
+    cells = p8["ncells"]
+
+    def timed(solver, n_steps, t_end):
+        solver.run(2, t_end=0.0)  # warm-up (then reset below)
+        return None
+
+    # level 8 reference: args.steps steps fix the end time
+    s8 = sme.Solver(p8, stream=st.cuda_stream)
+    s8.set_state(p8["q"])
+    s8.run(3)
+    s8.set_state(p8["q"])
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    s8.run(args.steps, sync=False)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms8 = e0.elapsed_time(e1)
+    T, n8 = s8.time()
+    ref = s8.get_state()
+    s8.close()
+    q1_init = closure._project_state(p8["q"], p8)
+    results = {}
+    for name, net in (("closure", mlp), ("plain", None)):
+        p1 = dict(p8, level=1, q=q1_init)
+        s1 = sme.Solver(p1, stream=st.cuda_stream)
+        if net is not None:
+            s1.attach_closure(net)
+        s1.set_state(q1_init)
+        s1.run(3)
+        s1.set_state(q1_init)
+        torch.cuda.synchronize()
+        e0.record(st)
+        s1.run(100 * args.steps, t_end=T, sync=False)
+        e1.record(st)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        t1_, n1 = s1.time()
+        q1 = s1.get_state()
+        oor = s1.out_of_range() if net is not None else 0
+        s1.close()
+        lifted = closure._lift_state(q1, p8)
+        err = closure.relative_l1(lifted, ref, fields=(0, 1))
+        results[name] = dict(ms=ms, steps=n1, t=t1_, err_h=err[0], err_hu=err[1], out_of_range=oor)
+    c, pl = results["closure"], results["plain"]
+    speedup = ms8 / c["ms"]
+    value = cells * c["steps"] / (c["ms"] * 1e-3)
+    alg = bytes_per_cell("2d", 1) * cells
+    out = {
+        "metric": "SME cell-updates/s (FP64 state, FP32 closure network)", "value": value,
+        "unit": "cell-updates/s", "n_gpus": 1, "steps": c["steps"], "warmup": 3,
+        "ms_per_step": c["ms"] / c["steps"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64+f32", "data": "synthetic",
+        "config": {"workload": wl["name"], "cells": cells, "t_end": T, "level8_steps": n8,
+                   "training": f"{args.closure_seeds} level-8 1D runs x {args.closure_steps} steps, "
+                               f"{feat.shape[0]} samples, {args.closure_epochs} epochs"},
+        "roofline": {"bound": "alu", "achieved": None, "peak": 157.3, "unit": "TFLOP/s", "frac": None,
+                     "traffic": None, "kernel": wl["kernel"], "alg_bytes_per_launch": alg,
+                     "avg_launch_us": c["ms"] * 1e3 / max(1, c["steps"]),
+                     "note": "network: 2 x 4,800 FP32 FMA per cell per step"},
+        "closure": {"speedup_vs_level8_same_time": speedup, "level8_ms": ms8, "level8_steps": n8,
+                    "level8_cell_updates_per_s": cells * n8 / (ms8 * 1e-3),
+                    "closure": c, "plain_level1": pl,
+                    "error_ratio_closure_over_plain": (c["err_h"] + c["err_hu"]) / (pl["err_h"] + pl["err_hu"])},
+        "cpu_baseline": None,
+    }
+    flops = 2 * 2 * 4800 * cells * c["steps"]
+    out["roofline"]["achieved"] = flops / (c["ms"] * 1e-3) / 1e12
+    out["roofline"]["frac"] = out["roofline"]["achieved"] / 157.3
     print(json.dumps(out), flush=True)
 
 

@@ -10,8 +10,10 @@ Target (a-priori closure): for consecutive level-8 states Q8^n, Q8^{n+1} with
 step dt, r = [P(Q8^{n+1}) - Step_L1(P(Q8^n))] / dt on (q_0, q_1), where P keeps
 (h, q_0, q_1) (the Legendre basis is orthogonal, so truncation is the
 projection).  Level 1 plus closure then advances Q1^{n+1} = Step_L1(Q1^n) + dt r(Q1^n).
-Outside the range of its training features the closure is not trusted: the
-level-1 run stops and the plain level-8 solver continues from the lifted state.
+Outside the range of its training features the network is not trusted: such a
+cell gets no correction in that step, and once more than a small fraction of
+cell-steps of a chunk were out of range the level-1 run stops and the plain
+level-8 solver continues from the lifted state.
 """
 import numpy as np
 import torch
@@ -145,10 +147,11 @@ class ClosureSolver:
     """Level 1 + closure on a 1D or structured grid, with the plain level-8
     solver as fallback once a cell's features leave the training range."""
 
-    def __init__(self, problem8, mlp, chunk=50, stream=None):
+    def __init__(self, problem8, mlp, chunk=50, stream=None, max_out_of_range=1e-3):
         self.p8 = problem8
         self.mlp = mlp
         self.chunk = chunk
+        self.max_oor = max_out_of_range  # tolerated fraction of out-of-range cell-steps
         self.stream = stream
         self.s1 = sme.Solver(_project_any(problem8), stream=stream)
         self.s1.attach_closure(mlp)
@@ -168,7 +171,8 @@ class ClosureSolver:
             t_keep = t
             self.s1.set_state(keep)  # fresh clock for the chunk
             dt_run, n = self.s1.run(self.chunk, t_end=t_end - t)
-            if self.s1.out_of_range() > 0:
+            cells = self.p8["ncells"]
+            if self.s1.out_of_range() > self.max_oor * cells * max(1, n):
                 # fall back: restart this chunk with level 8 from the lifted state
                 self.fell_back_at = t_keep
                 self.s8 = sme.Solver(self.p8, stream=self.stream)

@@ -57,6 +57,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_step(BatchArgs B)
         a.err = B.err;
         a.closure = nullptr;
         a.oor = nullptr;
+        a.rates = nullptr;
         const double dt = step_dt(a);
         if (item.sx == 0 && item.sy == 0 && lane == 0) slot_update(a, dt);
         double r = 0.0;

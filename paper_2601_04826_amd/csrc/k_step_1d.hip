@@ -4,8 +4,7 @@
 // each side); each lane computes the face to its right, the right cell's share
 // moves one lane up through a cross-lane shift.  With a learned closure
 // attached (level 1 only) every cell also adds dt times the network's
-// correction rates of (q_0, q_1), evaluated from the cell and its two
-// neighbours at the start of the step.
+// correction rates of (q_0, q_1), which the rates pass computed from Q^n.
 #include <hip/hip_runtime.h>
 
 #include "sme_step_common.h"
@@ -20,8 +19,6 @@ template <int N, bool CLOS>
 __global__ __launch_bounds__(kBlock) void k_step_1d(StepArgs a)
 {
     constexpr int n = N + 1;
-    extern __shared__ float lds_params[];
-    if constexpr (CLOS) mlp_stage(a.closure->params, lds_params);
     const double dt = step_dt(a);
     if (blockIdx.x == 0 && threadIdx.x == 0) slot_update(a, dt);
     const int lane = threadIdx.x & (kWave - 1);
@@ -62,14 +59,6 @@ __global__ __launch_bounds__(kBlock) void k_step_1d(StepArgs a)
             double oth = fma(0.5, D[f], -Fh[f]);
             acc[f] = own + shfl_up1(oth);
         }
-        double cr0 = 0.0, cr1 = 0.0;
-        bool inside = true;
-        if constexpr (CLOS) {
-            static_assert(N == 1, "the closure acts on level 1");
-            const double hm = shfl_up1(S.h), q0m = shfl_up1(S.qa[0]), q1m = shfl_up1(S.qa[1]);
-            inside = closure_rate(lds_params, a.closure, S.h, S.qa[0], S.qa[1], R.h, R.qa[0], R.qa[1], hm, q0m, q1m,
-                                  cr0, cr1);
-        }
         // predictor and friction
         const double sc = dt * a.idx;
         double h = fma(-sc, acc[0], S.h);
@@ -79,13 +68,14 @@ __global__ __launch_bounds__(kBlock) void k_step_1d(StepArgs a)
         const double ih = rcp(h);
         friction<N>(q, ih, dt, a.c_slip, a.nu);
         if constexpr (CLOS) {
-            q[0] = fma(dt, cr0, q[0]);
-            q[1] = fma(dt, cr1, q[1]);
+            static_assert(N == 1, "the closure acts on level 1");
+            if (out) {  // rates of (q_0, q_1) from the rates pass over Q^n
+                const float2 cr = reinterpret_cast<const float2 *>(a.rates)[c];
+                q[0] = fma(dt, (double)cr.x, q[0]);
+                q[1] = fma(dt, (double)cr.y, q[1]);
+            }
         }
         if (out) {
-            if constexpr (CLOS) {
-                if (!inside) atomicAdd(a.oor, 1ull);
-            }
             a.qn[c] = h;
             bool bad = !(h > 0.0) || !isfinite(h);
 #pragma unroll
@@ -110,7 +100,7 @@ hipError_t launch_step_1d(int level, const StepArgs &a, hipStream_t s)
     const unsigned grid = blocks_for(waves * kWave);
     if (a.closure) {
         if (level != 1) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((k_step_1d<1, true>), dim3(grid), dim3(kBlock), kMlpParams * sizeof(float), s, a);
+        hipLaunchKernelGGL((k_step_1d<1, true>), dim3(grid), dim3(kBlock), 0, s, a);
         return hipGetLastError();
     }
 #define L1(N) hipLaunchKernelGGL((k_step_1d<N, false>), dim3(grid), dim3(kBlock), 0, s, a)

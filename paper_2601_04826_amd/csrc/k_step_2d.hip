@@ -12,8 +12,6 @@ namespace {
 template <int N, bool CLOS>
 __global__ __launch_bounds__(kBlock) void k_step_2d(StepArgs a)
 {
-    extern __shared__ float lds_params[];
-    if constexpr (CLOS) mlp_stage(a.closure->params, lds_params);
     const double dt = step_dt(a);
     if (blockIdx.x == 0 && threadIdx.x == 0) slot_update(a, dt);
     const int nsx = (a.nx + kOut - 1) / kOut;
@@ -27,7 +25,7 @@ __global__ __launch_bounds__(kBlock) void k_step_2d(StepArgs a)
     const int wave = slot * (kBlock / kWave) + (threadIdx.x >> 6);
     double rmax = 0.0;
     if (wave < nsx * nsy)  // waves beyond the grid only join the reduction
-        rmax = band2d<N, CLOS>(a, dt, wave % nsx, wave / nsx, lds_params);
+        rmax = band2d<N, CLOS>(a, dt, wave % nsx, wave / nsx);
     publish_max(&a.slots[a.sb].rbits, rmax);
 }
 
@@ -42,7 +40,7 @@ hipError_t launch_step_2d(int level, const StepArgs &a, hipStream_t s)
     const unsigned grid = (unsigned)((blocks + kXcd - 1) / kXcd * kXcd);
     if (a.closure) {
         if (level != 1) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((k_step_2d<1, true>), dim3(grid), dim3(kBlock), kMlpParams * sizeof(float), s, a);
+        hipLaunchKernelGGL((k_step_2d<1, true>), dim3(grid), dim3(kBlock), 0, s, a);
         return hipGetLastError();
     }
 #define L2(N) hipLaunchKernelGGL((k_step_2d<N, false>), dim3(grid), dim3(kBlock), 0, s, a)

@@ -13,9 +13,7 @@
 //   * rows are loaded one at a time (registers go to occupancy rather than to
 //     a prefetched row).
 // With a learned closure (CLOS, level 1) each finished cell also adds dt times
-// the network's correction rates: along x from the cell and its two lane
-// neighbours, along y from the row below (kept in the cell) and
-// the row above.
+// the network's correction rates, computed from Q^n by the rates pass.
 // Every face value is computed from the same inputs by the same code whichever
 // wave computes it, so the result does not depend on how a grid is cut into
 // strips and bands.
@@ -38,9 +36,6 @@ struct Cell2 {
     double Fyy[n];        // y-frame normal block (y momenta), gravity included
     double Ft[n];         // tangential block, identical in both frames
     double lx, ly;        // wave-speed bounds along x and y
-    double dn[3];         // closure: (h, qy_0, qy_1) of the row below
-    double crx[2];        // closure: correction rates of (qx_0, qx_1) along x
-    bool inx;             // closure: x features inside the training box
 };
 
 template <int N>
@@ -164,8 +159,8 @@ __device__ __forceinline__ void y_face(const StepArgs &a, const Cell2<N> &P, con
 }
 
 // x-faces of the row of C: face to the right of each lane, neighbour via shuffle.
-template <int N, bool CLOS>
-__device__ __forceinline__ void x_faces(const StepArgs &a, Cell2<N> &C, double *accC, const float *Pl)
+template <int N>
+__device__ __forceinline__ void x_faces(const StepArgs &a, const Cell2<N> &C, double *accC)
 {
     constexpr int n = N + 1;
     constexpr int nf = 2 * n + 1;
@@ -181,11 +176,6 @@ __device__ __forceinline__ void x_faces(const StepArgs &a, Cell2<N> &C, double *
         R.Fa[k] = shfl_dn(X.Fa[k]);
         R.Ft[k] = shfl_dn(X.Ft[k]);
     }
-    if constexpr (CLOS) {
-        const double hm = shfl_up1(X.h), q0m = shfl_up1(X.qa[0]), q1m = shfl_up1(X.qa[1]);
-        C.inx = closure_rate(Pl, a.closure, X.h, X.qa[0], X.qa[1], R.h, R.qa[0], R.qa[1], hm, q0m, q1m, C.crx[0],
-                             C.crx[1]);
-    }
     double Gh[nf], E[nf];
     face_flux<N, true>(X, R, a.g, a.quad, Gh, E);
 #pragma unroll
@@ -199,15 +189,9 @@ __device__ __forceinline__ void x_faces(const StepArgs &a, Cell2<N> &C, double *
 // predictor, friction, store, CFL ratio of the new state
 template <int N, bool CLOS>
 __device__ __forceinline__ double finish_cell(const StepArgs &a, double dt, int64_t cell, bool out,
-                                              const Cell2<N> &c, const double *acc, const Cell2<N> &above,
-                                              const float *Pl)
+                                              const Cell2<N> &c, const double *acc)
 {
     constexpr int n = N + 1;
-    double cry0 = 0.0, cry1 = 0.0;
-    bool iny = true;
-    if constexpr (CLOS)
-        iny = closure_rate(Pl, a.closure, c.h, c.qy[0], c.qy[1], above.h, above.qy[0], above.qy[1], c.dn[0], c.dn[1],
-                           c.dn[2], cry0, cry1);
     const double h = fma(-dt, acc[0], c.h);
     double qx[n], qy[n];
 #pragma unroll
@@ -219,16 +203,18 @@ __device__ __forceinline__ double finish_cell(const StepArgs &a, double dt, int6
     friction<N>(qx, ih, dt, a.c_slip, a.nu);
     friction<N>(qy, ih, dt, a.c_slip, a.nu);
     if constexpr (CLOS) {
-        qx[0] = fma(dt, c.crx[0], qx[0]);
-        qx[1] = fma(dt, c.crx[1], qx[1]);
-        qy[0] = fma(dt, cry0, qy[0]);
-        qy[1] = fma(dt, cry1, qy[1]);
+        // learned closure: rates of (q_0, q_1) normal to x and to y from the rates pass
+        if (out) {
+            const float2 rx = reinterpret_cast<const float2 *>(a.rates)[cell];
+            const float2 ry = reinterpret_cast<const float2 *>(a.rates)[a.stride + cell];
+            qx[0] = fma(dt, (double)rx.x, qx[0]);
+            qx[1] = fma(dt, (double)rx.y, qx[1]);
+            qy[0] = fma(dt, (double)ry.x, qy[0]);
+            qy[1] = fma(dt, (double)ry.y, qy[1]);
+        }
     }
     double r = 0.0;
     if (out) {
-        if constexpr (CLOS) {
-            if (!(c.inx && iny)) atomicAdd(a.oor, 1ull);
-        }
         a.qn[cell] = h;
         double sum = h;
 #pragma unroll
@@ -250,35 +236,29 @@ __device__ __forceinline__ double finish_cell(const StepArgs &a, double dt, int6
 template <int N, bool CLOS>
 __device__ __forceinline__ void row(const StepArgs &a, double dt, Cell2<N> &P, double *accP, Cell2<N> &C,
                                     double *accC, const Raw2<N> &raw, int j, int c, bool outc, bool finish_p,
-                                    double &rmax, const float *Pl)
+                                    double &rmax)
 {
     cell_flux<N>(C, raw, a.g);
-    if constexpr (CLOS) {
-        C.dn[0] = P.h;
-        C.dn[1] = P.qy[0];
-        C.dn[2] = P.qy[1];
-    }
     y_face<N>(a, P, C, accP, accC, finish_p);
-    if (finish_p)
-        rmax = fmax(rmax, finish_cell<N, CLOS>(a, dt, (int64_t)(j - 1) * a.nx + c, outc, P, accP, C, Pl));
-    x_faces<N, CLOS>(a, C, accC, Pl);
+    if (finish_p) rmax = fmax(rmax, finish_cell<N, CLOS>(a, dt, (int64_t)(j - 1) * a.nx + c, outc, P, accP));
+    x_faces<N>(a, C, accC);
 }
 
 // closing y-face of the band: P is the last row (j1 - 1), raw the row above
 template <int N, bool CLOS>
 __device__ __forceinline__ void close_band(const StepArgs &a, double dt, Cell2<N> &P, double *accP,
                                            Cell2<N> &G, const Raw2<N> &raw, int j1, int c, bool outc,
-                                           double &rmax, const float *Pl)
+                                           double &rmax)
 {
     cell_flux<N>(G, raw, a.g);
     y_face<N>(a, P, G, accP, nullptr, true);
-    rmax = fmax(rmax, finish_cell<N, CLOS>(a, dt, (int64_t)(j1 - 1) * a.nx + c, outc, P, accP, G, Pl));
+    rmax = fmax(rmax, finish_cell<N, CLOS>(a, dt, (int64_t)(j1 - 1) * a.nx + c, outc, P, accP));
 }
 
 // Whole band (strip sx, band sy) of one grid: returns the largest CFL ratio
 // of the cells it wrote.  All 64 lanes of the wave must call it.
 template <int N, bool CLOS = false>
-__device__ __forceinline__ double band2d(const StepArgs &a, double dt, int sx, int sy, const float *Pl = nullptr)
+__device__ __forceinline__ double band2d(const StepArgs &a, double dt, int sx, int sy)
 {
     constexpr int n = N + 1;
     constexpr int nf = 2 * n + 1;
@@ -301,17 +281,17 @@ __device__ __forceinline__ double band2d(const StepArgs &a, double dt, int sx, i
     int j = j0;
     while (true) {
         Raw2<N> cur = nxt;
-        row<N, CLOS>(a, dt, A, accA, B, accB, cur, j, c, outc, j > j0, rmax, Pl);
+        row<N, CLOS>(a, dt, A, accA, B, accB, cur, j, c, outc, j > j0, rmax);
         load_row<N>(a, j + 1, col, mx, nxt);
         if (++j == j1) {
-            close_band<N, CLOS>(a, dt, B, accB, A, nxt, j1, c, outc, rmax, Pl);
+            close_band<N, CLOS>(a, dt, B, accB, A, nxt, j1, c, outc, rmax);
             break;
         }
         cur = nxt;
-        row<N, CLOS>(a, dt, B, accB, A, accA, cur, j, c, outc, true, rmax, Pl);
+        row<N, CLOS>(a, dt, B, accB, A, accA, cur, j, c, outc, true, rmax);
         load_row<N>(a, j + 1, col, mx, nxt);
         if (++j == j1) {
-            close_band<N, CLOS>(a, dt, A, accA, B, nxt, j1, c, outc, rmax, Pl);
+            close_band<N, CLOS>(a, dt, A, accA, B, nxt, j1, c, outc, rmax);
             break;
         }
     }

@@ -56,6 +56,7 @@ struct StepArgs {
     ErrWord *err;
     // learned closure (level 1 only; null = plain step)
     const ClosureModel *closure;
+    const float *rates;       // float2 rates of (q_0, q_1) normal to x at [cell], normal to y at [stride + cell]
     unsigned long long *oor;  // cells whose features left the training range
 };
 
@@ -111,6 +112,9 @@ hipError_t launch_mlp_adam(float *p, const float *g, float *m, float *v, float l
 hipError_t launch_closure_samples(const double *q8, int64_t s8, const double *q8n, int64_t s8n, const double *q1,
                                   int64_t s1, int64_t n, double dt, const int64_t *cells, int64_t ns, float *feat,
                                   float *targ, hipStream_t s);
+// closure rates of every cell from the current state (k_closure.hip)
+// dims = 1 (1D grid) or 2 (structured grid); mode 0 = FP32 network
+hipError_t launch_closure_rates(const StepArgs &a, int dims, int mode, hipStream_t s);
 hipError_t launch_permute(const double *src, int64_t sstride, double *dst, int64_t dstride,
                           const int64_t *map, int64_t ncells, int nf, hipStream_t s);
 

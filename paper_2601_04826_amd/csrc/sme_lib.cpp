@@ -60,6 +60,7 @@ struct sme_ctx {
     double *quad_dev = nullptr;      // Gauss points [kMaxQuad] then weights [kMaxQuad]
     ClosureModel *closure = nullptr;  // learned closure attached to a level-1 context
     unsigned long long *oor = nullptr;  // cells that left the closure's training range
+    float *rates = nullptr;             // closure rates of the current state (2 or 4 per cell)
     int cur = 0;   // which q[] holds the state
     int sa = 0;    // slot describing the current state
     bool has_state = false;
@@ -319,6 +320,7 @@ StepArgs make_args(const sme_ctx *c)
     a.err = c->err;
     a.closure = c->closure;
     a.oor = c->oor;
+    a.rates = c->rates;
     return a;
 }
 
@@ -327,7 +329,9 @@ hipError_t launch_one_step(sme_ctx *c, double dt_fixed, double t_end)
     StepArgs a = make_args(c);
     a.dt_fixed = dt_fixed;
     a.t_end = t_end;
-    hipError_t e;
+    hipError_t e = hipSuccess;
+    if (c->closure) e = launch_closure_rates(a, c->kind == SME_MESH_1D ? 1 : 2, 0, c->stream);
+    if (e != hipSuccess) return e;
     switch (c->kind) {
     case SME_MESH_1D: e = launch_step_1d(c->level, a, c->stream); break;
     case SME_MESH_2D_STRUCT: e = launch_step_2d(c->level, a, c->stream); break;
@@ -710,7 +714,9 @@ __attribute__((visibility("hidden"))) int sme_internal_attach(sme_ctx *c, const 
     if (!c) return SME_EINVAL;
     if (!m_host) {
         (void)hipFree(c->closure);
+        (void)hipFree(c->rates);
         c->closure = nullptr;
+        c->rates = nullptr;
         drop_graphs(c);
         return SME_OK;
     }
@@ -718,6 +724,10 @@ __attribute__((visibility("hidden"))) int sme_internal_attach(sme_ctx *c, const 
         return fail(c, SME_EINVAL, "the learned closure acts on level-1 1D and structured 2D grids");
     if (!c->closure) {
         if (dalloc(c, &c->closure, 1)) return SME_ENOMEM;
+    }
+    if (!c->rates) {
+        const int64_t per = c->kind == SME_MESH_1D ? 2 : 4;
+        if (dalloc(c, &c->rates, per * c->stride)) return SME_ENOMEM;
     }
     if (!c->oor) {
         if (dalloc(c, &c->oor, 1)) return SME_ENOMEM;
@@ -777,6 +787,7 @@ void sme_destroy(sme_ctx *c)
     (void)hipFree(c->quad_dev);
     (void)hipFree(c->closure);
     (void)hipFree(c->oor);
+    (void)hipFree(c->rates);
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }

@@ -31,6 +31,14 @@ struct ClosureModel {
     double box_hi[kMlpIn];
 };
 
+// tanh(z) = sign(z) (1 - e) / (1 + e), e = exp(-2|z|) in (0, 1]: no overflow,
+// absolute error about 1e-7.  Training and inference use this same function.
+__device__ __forceinline__ float tanh_f(float z)
+{
+    const float e = __expf(-2.0f * fabsf(z));
+    return copysignf(__fdividef(1.0f - e, 1.0f + e), z);
+}
+
 // copy the parameters of a model into LDS (all threads of the block call it)
 __device__ __forceinline__ void mlp_stage(const float *__restrict__ g, float *s)
 {
@@ -46,14 +54,14 @@ __device__ __forceinline__ void mlp_forward(const float *P, const float *x, floa
         float z = P[kOffB1 + j];
 #pragma unroll
         for (int i = 0; i < kMlpIn; ++i) z = fmaf(P[kOffW1 + j * kMlpIn + i], x[i], z);
-        a1[j] = tanhf(z);
+        a1[j] = tanh_f(z);
     }
 #pragma unroll
     for (int j = 0; j < kMlpHid; ++j) {
         float z = P[kOffB2 + j];
 #pragma unroll
         for (int i = 0; i < kMlpHid; ++i) z = fmaf(P[kOffW2 + j * kMlpHid + i], a1[i], z);
-        a2[j] = tanhf(z);
+        a2[j] = tanh_f(z);
     }
 #pragma unroll
     for (int o = 0; o < kMlpOut; ++o) {
@@ -68,14 +76,39 @@ __device__ __forceinline__ void mlp_forward(const float *P, const float *x, floa
 
 namespace sme {
 
+// Inference of one sample: y~ for normalised inputs x; layer 2 and 3 are
+// fused so that only the first hidden layer is held in registers.
+__device__ __forceinline__ void mlp_infer(const float *P, const float *x, float *y)
+{
+    float a1[kMlpHid];
+#pragma unroll
+    for (int j = 0; j < kMlpHid; ++j) {
+        float z = P[kOffB1 + j];
+#pragma unroll
+        for (int i = 0; i < kMlpIn; ++i) z = fmaf(P[kOffW1 + j * kMlpIn + i], x[i], z);
+        a1[j] = tanh_f(z);
+    }
+    float y0 = P[kOffB3], y1 = P[kOffB3 + 1];
+    for (int j = 0; j < kMlpHid; ++j) {
+        float z = P[kOffB2 + j];
+#pragma unroll
+        for (int i = 0; i < kMlpHid; ++i) z = fmaf(P[kOffW2 + j * kMlpHid + i], a1[i], z);
+        const float a2 = tanh_f(z);
+        y0 = fmaf(P[kOffW3 + j], a2, y0);
+        y1 = fmaf(P[kOffW3 + kMlpHid + j], a2, y1);
+    }
+    y[0] = y0;
+    y[1] = y1;
+}
+
 // Closure correction rates of the two normal momentum moments of one cell
 // along one direction.  Features: the cell's (h, q_0, q_1), its differences to
 // the neighbour ahead (p) and behind (m) along the direction.  P = parameters
 // in LDS, M = the model (normalisation, output scale, training box).
-// Returns false if a feature lies outside the training box.
+// Returns false (and zero rates) if a feature lies outside the training box.
 __device__ __forceinline__ bool closure_rate(const float *P, const ClosureModel *M, double h, double q0, double q1,
                                              double hp, double q0p, double q1p, double hm, double q0m, double q1m,
-                                             double &r0, double &r1)
+                                             float &r0, float &r1)
 {
     const double f[kMlpIn] = {h, q0, q1, hp - h, q0p - q0, q1p - q1, h - hm, q0 - q0m, q1 - q1m};
     float x[kMlpIn];
@@ -85,10 +118,10 @@ __device__ __forceinline__ bool closure_rate(const float *P, const ClosureModel 
         inside &= (f[i] >= M->box_lo[i]) & (f[i] <= M->box_hi[i]);
         x[i] = ((float)f[i] - M->mu[i]) * M->inv_sigma[i];
     }
-    float a1[kMlpHid], a2[kMlpHid], y[kMlpOut];
-    mlp_forward(P, x, a1, a2, y);
-    r0 = (double)(y[0] * M->out_scale[0]);
-    r1 = (double)(y[1] * M->out_scale[1]);
+    float y[kMlpOut];
+    mlp_infer(P, x, y);
+    r0 = inside ? y[0] * M->out_scale[0] : 0.0f;
+    r1 = inside ? y[1] * M->out_scale[1] : 0.0f;
     return inside;
 }
 

@@ -83,6 +83,23 @@ __device__ __forceinline__ void publish_max(unsigned long long *dst, double v)
     }
 }
 
+// Block-wide sum of a per-lane count, one atomic add per block if nonzero.
+// Every thread of the block must call it.
+__device__ __forceinline__ void publish_count(unsigned long long *dst, unsigned v)
+{
+    __shared__ unsigned part[kBlock / kWave];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    if ((threadIdx.x & (kWave - 1)) == 0) part[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long s = 0;
+#pragma unroll
+        for (int w = 0; w < kBlock / kWave; ++w) s += part[w];
+        if (s) atomicAdd(dst, s);
+    }
+}
+
 // record a non-physical value (h <= 0 or non-finite) produced by step `step`
 __device__ __forceinline__ void flag_bad_at(const StepArgs &a, bool bad, long long step)
 {

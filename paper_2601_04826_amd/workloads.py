@@ -19,6 +19,10 @@ tri_2d            Delaunay triangulation of 2,000,000 points U[0, 1]^2 (seed 2),
                   16 Gaussians (a ~ U(0, 0.2), sigma ~ U(0.02, 0.1), seed 3);
                   circular dam: depth 2 m inside r < 0.25 around (0.5, 0.5), 1 m
                   outside; 100 steps.
+smooth_1d/2d      random smooth periodic fields (sums of low Fourier modes) at any
+                  level: the training runs (1D, 4096 cells, seeds 1000..1255,
+                  held out 1256..1287) and the 2D evaluation (2048^2, seed 2000)
+                  of the learned closure.
 batch             512 instances on [0, 1]^2, side U{64..512}, level U{1..4}, walls,
                   flat bed, dam centre U[0.25, 0.75]^2, radius U(0.05, 0.2), inner
                   depth U(1, 3) m, outer 1 m (seed 4); 500 steps.
@@ -75,6 +79,41 @@ def smooth_1d(n=4096, level=8, seed=1000, steps=2000, L=10.0, params=None):
         q[1 + j] = h * amp * (1.0 + np.sin(2 * np.pi * mode * x / L + rng.uniform(0, 2 * np.pi)))
     return _problem("1d", level, n, q, np.zeros(n), steps, params,
                     nx=n, ny=1, x0=0.0, x1=L, y0=0.0, y1=1.0, bc=("periodic",) * 4)
+
+
+def smooth_2d(n=2048, level=8, seed=2000, steps=1000, L=10.0, params=None):
+    """Random smooth periodic 2D state from the family of ``smooth_1d``: depth
+    and both mean velocities are sums of four Fourier modes (wave number m along
+    x or y, random phases), each moment j >= 1 a scaled random mode (evaluation
+    of the learned closure)."""
+    rng = np.random.default_rng(seed)
+    d = L / n
+    jj, ii = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    x = ((ii + 0.5) * d).ravel()
+    y = ((jj + 0.5) * d).ravel()
+
+    def mode(m, amp):
+        # wave number m along x or along y (so each direction sees the 1D family)
+        kx, ky = (m, 0) if rng.integers(0, 2) == 0 else (0, m)
+        return amp * np.sin(2 * np.pi * (kx * x + ky * y) / L + rng.uniform(0, 2 * np.pi))
+
+    h = np.ones(n * n)
+    u = np.zeros(n * n)
+    v = np.zeros(n * n)
+    for m in range(1, 5):
+        h += mode(m, rng.uniform(-0.3, 0.3) / m)
+        u += mode(m, rng.uniform(-0.5, 0.5) / m)
+        v += mode(m, rng.uniform(-0.5, 0.5) / m)
+    k = level + 1
+    q = np.zeros((nfields(level, 2), n * n))
+    q[0] = h
+    q[1] = h * u
+    q[1 + k] = h * v
+    for j in range(1, level + 1):
+        q[1 + j] = h * rng.uniform(-0.3, 0.3) / j ** 2 * (1.0 + mode(rng.integers(1, 4), 1.0))
+        q[1 + k + j] = h * rng.uniform(-0.3, 0.3) / j ** 2 * (1.0 + mode(rng.integers(1, 4), 1.0))
+    return _problem("2d", level, n * n, q, np.zeros(n * n), steps, params,
+                    nx=n, ny=n, x0=0.0, x1=L, y0=0.0, y1=L, bc=("periodic",) * 4)
 
 
 def _periodic_gaussians(xc, yc, L, n, amp, sig, rng):

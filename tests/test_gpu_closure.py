@@ -207,7 +207,22 @@ def test_out_of_range_flag(env):
     s.attach_closure(m)
     s.set_state(prob["q"])
     s.run(3)
-    assert s.out_of_range() > 0
+    n_out = s.out_of_range()
+    assert n_out > 0
+    # a network that is not trusted anywhere leaves plain level 1
+    m2 = sme.MLP(rand_params(9))
+    m2.set_scaling(np.zeros(9), np.ones(9), np.ones(2), np.full(9, 1e3), np.full(9, 2e3))
+    s.attach_closure(m2)
+    s.set_state(prob["q"])
+    s.run(10)
+    off = s.get_state()
+    assert s.out_of_range() == 10 * prob["ncells"]
+    p = sme.Solver(prob)
+    p.set_state(prob["q"])
+    p.run(10)
+    assert np.array_equal(off, p.get_state())
+    p.close()
+    m2.close()
     hi[0] = 1e3
     m.set_scaling(np.zeros(9), np.ones(9), np.ones(2), lo, hi)
     s.attach_closure(m)
