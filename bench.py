@@ -101,6 +101,8 @@ def main():
     ap.add_argument("--closure-seeds", type=int, default=64, help="closure: level-8 training runs")
     ap.add_argument("--closure-steps", type=int, default=1000, help="closure: steps per training run")
     ap.add_argument("--closure-epochs", type=int, default=15)
+    ap.add_argument("--closure-precision", default="fp16", choices=["fp16", "fp32"],
+                    help="closure: network evaluation whose throughput is the headline value")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (read + write), 5 times: "
                          "calibrates the HBM byte counters against a kernel of known traffic")
@@ -248,11 +250,11 @@ def bench_closure(args, wl, torch, sme, workloads):
     s8.close()
     q1_init = closure._project_state(p8["q"], p8)
     results = {}
-    for name, net in (("closure", mlp), ("plain", None)):
+    for name, net, prec in (("closure_fp16", mlp, "fp16"), ("closure_fp32", mlp, "fp32"), ("plain", None, None)):
         p1 = dict(p8, level=1, q=q1_init)
         s1 = sme.Solver(p1, stream=st.cuda_stream)
         if net is not None:
-            s1.attach_closure(net)
+            s1.attach_closure(net, precision=prec)
         s1.set_state(q1_init)
         s1.run(3)
         s1.set_state(q1_init)
@@ -269,31 +271,37 @@ def bench_closure(args, wl, torch, sme, workloads):
         lifted = closure._lift_state(q1, p8)
         err = closure.relative_l1(lifted, ref, fields=(0, 1))
         results[name] = dict(ms=ms, steps=n1, t=t1_, err_h=err[0], err_hu=err[1], out_of_range=oor)
-    c, pl = results["closure"], results["plain"]
-    speedup = ms8 / c["ms"]
+    pl = results["plain"]
+    for r in results.values():
+        r["speedup_vs_level8_same_time"] = ms8 / r["ms"]
+        r["error_ratio_over_plain_level1"] = (r["err_h"] + r["err_hu"]) / (pl["err_h"] + pl["err_hu"])
+    c = results["closure_" + args.closure_precision]
     value = cells * c["steps"] / (c["ms"] * 1e-3)
     alg = bytes_per_cell("2d", 1) * cells
+    # network work per cell and step: two directions x (9x64 + 64x64 + 64x2) multiply-adds
+    flops = 2 * 2 * (9 * 64 + 64 * 64 + 64 * 2) * cells * c["steps"]
+    fp16 = args.closure_precision == "fp16"
+    peak = 2500.0 if fp16 else 157.3
+    achieved = flops / (c["ms"] * 1e-3) / 1e12
     out = {
-        "metric": "SME cell-updates/s (FP64 state, FP32 closure network)", "value": value,
+        "metric": "SME cell-updates/s, level 1 + learned closure (FP64 state, " +
+                  ("FP16-operand matrix-core" if fp16 else "FP32") + " network)", "value": value,
         "unit": "cell-updates/s", "n_gpus": 1, "steps": c["steps"], "warmup": 3,
         "ms_per_step": c["ms"] / c["steps"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64+f32", "data": "synthetic",
+        "dtype": "f64+f16mfma" if fp16 else "f64+f32", "data": "synthetic",
         "config": {"workload": wl["name"], "cells": cells, "t_end": T, "level8_steps": n8,
                    "training": f"{args.closure_seeds} level-8 1D runs x {args.closure_steps} steps, "
                                f"{feat.shape[0]} samples, {args.closure_epochs} epochs"},
-        "roofline": {"bound": "alu", "achieved": None, "peak": 157.3, "unit": "TFLOP/s", "frac": None,
-                     "traffic": None, "kernel": wl["kernel"], "alg_bytes_per_launch": alg,
-                     "avg_launch_us": c["ms"] * 1e3 / max(1, c["steps"]),
-                     "note": "network: 2 x 4,800 FP32 FMA per cell per step"},
-        "closure": {"speedup_vs_level8_same_time": speedup, "level8_ms": ms8, "level8_steps": n8,
-                    "level8_cell_updates_per_s": cells * n8 / (ms8 * 1e-3),
-                    "closure": c, "plain_level1": pl,
-                    "error_ratio_closure_over_plain": (c["err_h"] + c["err_hu"]) / (pl["err_h"] + pl["err_hu"])},
+        "roofline": {"bound": "mfma" if fp16 else "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": None,
+                     "kernel": "k_closure_rates_mfma + k_step_2d<1,closure>" if fp16 else
+                               "k_closure_rates_valu + k_step_2d<1,closure>",
+                     "alg_bytes_per_launch": alg, "avg_launch_us": c["ms"] * 1e3 / max(1, c["steps"]),
+                     "note": "network flops over the whole level-1 + closure step time"},
+        "closure": {"level8_ms": ms8, "level8_steps": n8, "level8_cell_updates_per_s": cells * n8 / (ms8 * 1e-3),
+                    "level8_err_budget": {"err_h": pl["err_h"], "err_hu": pl["err_hu"]}, **results},
         "cpu_baseline": None,
     }
-    flops = 2 * 2 * 4800 * cells * c["steps"]
-    out["roofline"]["achieved"] = flops / (c["ms"] * 1e-3) / 1e12
-    out["roofline"]["frac"] = out["roofline"]["achieved"] / 157.3
     print(json.dumps(out), flush=True)
 
 

@@ -220,8 +220,18 @@ int sme_closure_samples(const double *q8, int64_t stride8, const double *q8_next
                         const double *q1_step, int64_t stride1, int64_t ncells, double dt,
                         const int64_t *cells, int64_t nsamples, float *feat, float *targ, void *stream);
 /* Attach the network (copied) to a level-1 1D or structured context; NULL
- * detaches.  Every later step adds the correction. */
+ * detaches.  Before every later step a rates pass evaluates the network on
+ * the current state (every cell and direction); the step adds dt times the
+ * rates.  sme_closure_attach evaluates it in FP32 (SME_CLOSURE_FP32).
+ * sme_closure_attach_ex can instead choose SME_CLOSURE_FP16_MFMA: matrix-core
+ * products with FP16 weights and activations and FP32 accumulation (feature
+ * normalisation, activations and output scaling in FP32); its rates differ from
+ * the FP32 ones by about 1e-3 relative.  SME_EINVAL for an unknown precision
+ * or weights beyond the FP16 range. */
+#define SME_CLOSURE_FP32 0
+#define SME_CLOSURE_FP16_MFMA 1
 int sme_closure_attach(sme_ctx *ctx, const sme_mlp *m);
+int sme_closure_attach_ex(sme_ctx *ctx, const sme_mlp *m, int precision);
 /* Cell-steps whose features left the training box since sme_set_state. */
 int sme_closure_out_of_range(sme_ctx *ctx, int64_t *cells);
 

@@ -6,8 +6,21 @@
 // along that direction, boundary ghosts as in the step), evaluates the network
 // and stores the two correction rates as FP32 float2 at [dir * stride + cell].
 // A direction whose features leave the training box gets zero rates and is
-// counted.  The network's parameters are staged in LDS.
+// counted.
+//
+// Two evaluations of the network:
+//   FP32   one lane per sample, parameters staged in LDS, FP32 FMA chains;
+//   FP16   matrix cores: a wave evaluates 64 samples as four 16-sample tiles,
+//          every layer one or two v_mfma_f32_16x16x{16,32}_f16 per 16 units
+//          (FP16 operands, FP32 accumulation).  Result lane layout of a
+//          16x16 tile: lane l holds rows 4 (l / 16) + {0..3} of column l % 16;
+//          operand lanes hold row (A) or column (B) l % 16 and the k-slice
+//          [K/4 (l / 16), K/4 (l / 16 + 1)).  Hidden units are rows, samples
+//          columns, so the activations of one layer are already the B operand
+//          of the next (the folded weights carry the matching column order).
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include "sme_step_common.h"
 
@@ -59,11 +72,153 @@ __global__ __launch_bounds__(kBlock) void k_closure_rates_valu(StepArgs a, unsig
     publish_count(a.oor, out);
 }
 
+
+typedef _Float16 half4 __attribute__((ext_vector_type(4)));
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef float float4v __attribute__((ext_vector_type(4)));
+
+// raw features of sample (cell, dir) and whether they lie in the training box;
+// x = normalised features (FP32, same arithmetic as the FP32 variant)
+__device__ __forceinline__ bool sample_features(const StepArgs &a, int64_t cell, int dir, float *x)
+{
+    const ClosureModel *M = a.closure;
+    const int i = (int)(cell % a.nx), j = (int)(cell / a.nx);
+    const int blk = dir ? 3 : 1;
+    const double h = a.q[cell];
+    const double q0 = a.q[blk * a.stride + cell], q1 = a.q[(blk + 1) * a.stride + cell];
+    double hp, q0p, q1p, hm, q0m, q1m;
+    nb_normal(a, i, j, dir ? 0 : 1, dir, blk, hp, q0p, q1p);
+    nb_normal(a, i, j, dir ? 0 : -1, -dir, blk, hm, q0m, q1m);
+    const double f[kMlpIn] = {h, q0, q1, hp - h, q0p - q0, q1p - q1, h - hm, q0 - q0m, q1 - q1m};
+    bool inside = true;
+#pragma unroll
+    for (int k = 0; k < kMlpIn; ++k) {
+        inside &= (f[k] >= M->box_lo[k]) & (f[k] <= M->box_hi[k]);
+        x[k] = ((float)f[k] - M->mu[k]) * M->inv_sigma[k];
+    }
+    return inside;
+}
+
+// tanh(u / kappa) = 1 - 2 / (1 + 2^u), rounded to FP16 (exact limits +-1 for |u| -> inf)
+__device__ __forceinline__ _Float16 act(float u)
+{
+    return (_Float16)fmaf(-2.0f, __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(u)), 1.0f);
+}
+
+// activations of the result tiles 2 kc and 2 kc + 1 as the B operand of chunk kc
+__device__ __forceinline__ half8 act_pair(const float4v &lo, const float4v &hi)
+{
+    half8 s;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        s[e] = act(lo[e]);
+        s[4 + e] = act(hi[e]);
+    }
+    return s;
+}
+
+constexpr int kGroup = 64;  // samples per wave and pass
+
+// groups of 64 consecutive cells, direction-major: group k covers direction
+// k / per_dir; waves stride over the groups
+__global__ __launch_bounds__(kBlock) void k_closure_rates_mfma(StepArgs a, int64_t per_dir, int64_t ngroups)
+{
+    __shared__ __attribute__((aligned(16))) _Float16 X[kBlock / kWave][kGroup][kMlpInPad];
+    const ClosureFp16 &H = a.closure->h;
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x >> 6;
+    const int g = lane >> 4, col = lane & 15;
+    half4 w1[4];
+    half8 w2[4][2], w3[2];
+    float4v c1[4], c2[4], c3;
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+        w1[mt] = *reinterpret_cast<const half4 *>(&H.w1[16 * mt + col][4 * g]);
+#pragma unroll
+        for (int kc = 0; kc < 2; ++kc) w2[mt][kc] = *reinterpret_cast<const half8 *>(&H.w2[16 * mt + col][32 * kc + 8 * g]);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            c1[mt][r] = H.c1[16 * mt + 4 * g + r];
+            c2[mt][r] = H.c2[16 * mt + 4 * g + r];
+        }
+    }
+#pragma unroll
+    for (int kc = 0; kc < 2; ++kc) w3[kc] = *reinterpret_cast<const half8 *>(&H.w3[col][32 * kc + 8 * g]);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) c3[r] = g == 0 ? H.c3[r] : 0.0f;
+    const float os0 = a.closure->out_scale[0], os1 = a.closure->out_scale[1];
+    const bool live = step_dt(a) > 0.0;  // a step past the end time changes nothing
+    const int64_t nwaves = (int64_t)gridDim.x * (kBlock / kWave);
+    unsigned out = 0;
+    for (int64_t grp = (int64_t)blockIdx.x * (kBlock / kWave) + wv; grp < ngroups; grp += nwaves) {
+        const int dir = grp >= per_dir ? 1 : 0;
+        const int64_t cell0 = (grp - dir * per_dir) * kGroup;
+        float2 *rates = reinterpret_cast<float2 *>(const_cast<float *>(a.rates)) + dir * a.stride;
+        // features: one sample per lane
+        {
+            const int64_t cell = cell0 + lane;
+            float x[kMlpIn];
+#pragma unroll
+            for (int k = 0; k < kMlpIn; ++k) x[k] = 0.0f;
+            bool inside = false;
+            if (cell < a.ncells && live) {
+                inside = sample_features(a, cell, dir, x);
+                out += inside ? 0u : 1u;
+            }
+            half8 lo, hi;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                lo[k] = (_Float16)x[k];
+                hi[k] = k == 0 ? (_Float16)x[8] : (_Float16)0.0f;
+            }
+            *reinterpret_cast<half8 *>(&X[wv][lane][0]) = lo;
+            *reinterpret_cast<half8 *>(&X[wv][lane][8]) = hi;
+            // keep: the in-box flag of every sample of the group
+            const unsigned long long inmask = __ballot(inside);
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll 1
+            for (int t = 0; t < kGroup / 16; ++t) {
+                const half4 xb = *reinterpret_cast<const half4 *>(&X[wv][16 * t + col][4 * g]);
+                float4v u1[4];
+#pragma unroll
+                for (int mt = 0; mt < 4; ++mt) u1[mt] = __builtin_amdgcn_mfma_f32_16x16x16f16(w1[mt], xb, c1[mt], 0, 0, 0);
+                const half8 s10 = act_pair(u1[0], u1[1]), s11 = act_pair(u1[2], u1[3]);
+                float4v u2[4];
+#pragma unroll
+                for (int mt = 0; mt < 4; ++mt) {
+                    u2[mt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(w2[mt][0], s10, c2[mt], 0, 0, 0);
+                    u2[mt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(w2[mt][1], s11, u2[mt], 0, 0, 0);
+                }
+                const half8 s20 = act_pair(u2[0], u2[1]), s21 = act_pair(u2[2], u2[3]);
+                float4v y = __builtin_amdgcn_mfma_f32_16x16x32_f16(w3[0], s20, c3, 0, 0, 0);
+                y = __builtin_amdgcn_mfma_f32_16x16x32_f16(w3[1], s21, y, 0, 0, 0);
+                const int smp = 16 * t + col;
+                const int64_t c = cell0 + smp;
+                if (g == 0 && c < a.ncells) {
+                    const bool ok = ((inmask >> smp) & 1ull) != 0;
+                    rates[c] = ok ? make_float2(os0 * y[0], os1 * y[1]) : make_float2(0.0f, 0.0f);
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+    publish_count(a.oor, out);
+}
+
 }  // namespace
 
-hipError_t launch_closure_rates(const StepArgs &a, int dims, int mode, hipStream_t s)
+hipError_t launch_closure_rates(const StepArgs &a, int dims, int mode, int cus, hipStream_t s)
 {
-    if (mode != 0 || dims < 1 || dims > 2) return hipErrorInvalidValue;
+    if (dims < 1 || dims > 2) return hipErrorInvalidValue;
+    if (mode == kClosureFp16Mfma) {
+        const int64_t per_dir = (a.ncells + kGroup - 1) / kGroup;
+        const int64_t ngroups = per_dir * dims;
+        // enough blocks to fill every SIMD several times; waves stride over the rest
+        const int64_t want = (ngroups + kBlock / kWave - 1) / (kBlock / kWave);
+        const unsigned grid = (unsigned)std::min<int64_t>(want, (int64_t)cus * 8);
+        hipLaunchKernelGGL(k_closure_rates_mfma, dim3(grid), dim3(kBlock), 0, s, a, per_dir, ngroups);
+        return hipGetLastError();
+    }
+    if (mode != kClosureFp32) return hipErrorInvalidValue;
     const unsigned nblk = blocks_for(a.ncells);
     const unsigned dirs = (unsigned)dims;
     hipLaunchKernelGGL(k_closure_rates_valu, dim3(nblk * dirs), dim3(kBlock), 0, s, a, nblk);

@@ -68,6 +68,34 @@ int ensure_partials(sme_mlp *m, int64_t batch)
     return SME_OK;
 }
 
+// Operands of the FP16 matrix-core inference (see ClosureFp16): kappa =
+// 2 log2(e) folded into the first two layers, columns of the second and third
+// layer in the lane order of the previous result; one rounding each.
+// False if a folded weight does not fit FP16.
+bool fold_fp16(ClosureModel &cm)
+{
+    const double kappa = 2.0 / std::log(2.0);
+    const float *P = cm.params;
+    ClosureFp16 &H = cm.h;
+    std::memset(&H, 0, sizeof H);
+    double wmax = 0.0;
+    auto put = [&wmax](_Float16 &dst, double v) {
+        wmax = std::fmax(wmax, std::fabs(v));
+        dst = (_Float16)(float)v;
+    };
+    for (int j = 0; j < kMlpHid; ++j) {
+        for (int i = 0; i < kMlpIn; ++i) put(H.w1[j][i], kappa * P[kOffW1 + j * kMlpIn + i]);
+        H.c1[j] = (float)(kappa * P[kOffB1 + j]);
+        for (int p = 0; p < kMlpHid; ++p) put(H.w2[j][p], kappa * P[kOffW2 + j * kMlpHid + kFoldPerm(p)]);
+        H.c2[j] = (float)(kappa * P[kOffB2 + j]);
+    }
+    for (int o = 0; o < kMlpOut; ++o) {
+        for (int p = 0; p < kMlpHid; ++p) put(H.w3[o][p], P[kOffW3 + o * kMlpHid + kFoldPerm(p)]);
+        H.c3[o] = P[kOffB3 + o];
+    }
+    return wmax <= 65504.0;
+}
+
 }  // namespace
 
 extern "C" {
@@ -220,17 +248,28 @@ int sme_closure_samples(const double *q8, int64_t stride8, const double *q8_next
     return e == hipSuccess ? SME_OK : SME_EHIP;
 }
 
-int sme_closure_attach(sme_ctx *ctx, const sme_mlp *m)
+int sme_closure_attach_ex(sme_ctx *ctx, const sme_mlp *m, int precision)
 {
     if (!ctx) return SME_EINVAL;
     if (!m) return sme_internal_attach(ctx, nullptr);
-    ClosureModel cm = m->host;
+    if (precision != SME_CLOSURE_FP32 && precision != SME_CLOSURE_FP16_MFMA) return SME_EINVAL;
+    ClosureModel *cm = new (std::nothrow) ClosureModel(m->host);
+    if (!cm) return SME_ENOMEM;
     // the parameters come from the device copy
     sme_mlp *mm = const_cast<sme_mlp *>(m);
-    MCHK(mm, hipMemcpyAsync(cm.params, m->p, kMlpParams * sizeof(float), hipMemcpyDeviceToHost, m->stream));
-    MCHK(mm, hipStreamSynchronize(m->stream));
-    return sme_internal_attach(ctx, &cm);
+    mm->last.clear();
+    hipError_t e = hipMemcpyAsync(cm->params, m->p, kMlpParams * sizeof(float), hipMemcpyDeviceToHost, m->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
+    int rc = e == hipSuccess ? SME_OK : mfail(mm, SME_EHIP, "parameter copy failed: %s", hipGetErrorString(e));
+    cm->precision = precision == SME_CLOSURE_FP16_MFMA ? kClosureFp16Mfma : kClosureFp32;
+    if (rc == SME_OK && precision == SME_CLOSURE_FP16_MFMA && !fold_fp16(*cm))
+        rc = mfail(mm, SME_EINVAL, "folded weights exceed the FP16 range");
+    if (rc == SME_OK) rc = sme_internal_attach(ctx, cm);
+    delete cm;
+    return rc;
 }
+
+int sme_closure_attach(sme_ctx *ctx, const sme_mlp *m) { return sme_closure_attach_ex(ctx, m, SME_CLOSURE_FP32); }
 
 int sme_closure_out_of_range(sme_ctx *ctx, int64_t *cells)
 {

@@ -113,8 +113,8 @@ hipError_t launch_closure_samples(const double *q8, int64_t s8, const double *q8
                                   int64_t s1, int64_t n, double dt, const int64_t *cells, int64_t ns, float *feat,
                                   float *targ, hipStream_t s);
 // closure rates of every cell from the current state (k_closure.hip)
-// dims = 1 (1D grid) or 2 (structured grid); mode 0 = FP32 network
-hipError_t launch_closure_rates(const StepArgs &a, int dims, int mode, hipStream_t s);
+// dims = 1 (1D grid) or 2 (structured grid); mode = ClosurePrecision; cus = compute units
+hipError_t launch_closure_rates(const StepArgs &a, int dims, int mode, int cus, hipStream_t s);
 hipError_t launch_permute(const double *src, int64_t sstride, double *dst, int64_t dstride,
                           const int64_t *map, int64_t ncells, int nf, hipStream_t s);
 

@@ -61,6 +61,8 @@ struct sme_ctx {
     ClosureModel *closure = nullptr;  // learned closure attached to a level-1 context
     unsigned long long *oor = nullptr;  // cells that left the closure's training range
     float *rates = nullptr;             // closure rates of the current state (2 or 4 per cell)
+    int closure_mode = 0;               // ClosurePrecision of the attached network
+    int cus = 256;                      // compute units of the device
     int cur = 0;   // which q[] holds the state
     int sa = 0;    // slot describing the current state
     bool has_state = false;
@@ -330,7 +332,7 @@ hipError_t launch_one_step(sme_ctx *c, double dt_fixed, double t_end)
     a.dt_fixed = dt_fixed;
     a.t_end = t_end;
     hipError_t e = hipSuccess;
-    if (c->closure) e = launch_closure_rates(a, c->kind == SME_MESH_1D ? 1 : 2, 0, c->stream);
+    if (c->closure) e = launch_closure_rates(a, c->kind == SME_MESH_1D ? 1 : 2, c->closure_mode, c->cus, c->stream);
     if (e != hipSuccess) return e;
     switch (c->kind) {
     case SME_MESH_1D: e = launch_step_1d(c->level, a, c->stream); break;
@@ -733,8 +735,12 @@ __attribute__((visibility("hidden"))) int sme_internal_attach(sme_ctx *c, const 
         if (dalloc(c, &c->oor, 1)) return SME_ENOMEM;
         HIPCHK(c, hipMemset(c->oor, 0, sizeof(unsigned long long)));
     }
+    if (m_host->precision != kClosureFp32 && m_host->precision != kClosureFp16Mfma)
+        return fail(c, SME_EINVAL, "unknown closure precision %d", m_host->precision);
     HIPCHK(c, hipMemcpyAsync(c->closure, m_host, sizeof(ClosureModel), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->closure_mode = m_host->precision;
+    c->cus = host::device_cus();
     drop_graphs(c);
     return SME_OK;
 }

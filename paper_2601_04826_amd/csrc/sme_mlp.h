@@ -10,6 +10,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cstddef>
+
 namespace sme {
 
 constexpr int kMlpIn = 9, kMlpHid = 64, kMlpOut = 2;
@@ -21,7 +23,35 @@ constexpr int kOffW3 = kOffB2 + kMlpHid;
 constexpr int kOffB3 = kOffW3 + kMlpOut * kMlpHid;
 constexpr int kMlpParams = kOffB3 + kMlpOut;  // 4930
 
-// Everything the fused level-1 step needs besides the parameters.
+// Reduced-precision inference: FP16 matrix-core operands, FP32 accumulation.
+// With kappa = 2 log2(e), a layer computes u = kappa (W a + b) on the matrix
+// cores (kappa folded into the FP16 weights and FP32 biases on the host) and
+// tanh(u / kappa) = 1 - 2 / (1 + 2^u) in FP32 (one exp2, one add, one
+// reciprocal, one FMA), rounded once to FP16 as the next layer's operand.
+// The columns of w2 and w3 are stored in the order in which the matrix-core
+// result of the previous layer lands in the lanes (kFoldPerm), so activations
+// feed the next product without any data movement.
+constexpr int kMlpInPad = 16;
+struct alignas(16) ClosureFp16 {
+    _Float16 w1[kMlpHid][kMlpInPad];  // kappa W1, inputs 9..15 zero
+    _Float16 w2[kMlpHid][kMlpHid];    // kappa W2, permuted columns
+    _Float16 w3[16][kMlpHid];         // W3, permuted columns, rows 2..15 zero
+    float c1[kMlpHid];                // kappa b1
+    float c2[kMlpHid];                // kappa b2
+    float c3[4];                      // b3, rows 2, 3 zero
+};
+
+// Column p = 32 kc + 8 g + e of a folded matrix holds hidden unit kFoldPerm(p):
+// the 16x16 result tiles 2 kc and 2 kc + 1 give lane group g the units
+// 16 (2 kc) + 4 g + {0..3} and 16 (2 kc + 1) + 4 g + {0..3}.
+constexpr int kFoldPerm(int p)
+{
+    return 32 * (p / 32) + ((p % 8) < 4 ? 4 * ((p % 32) / 8) + (p % 8) : 16 + 4 * ((p % 32) / 8) + (p % 8) - 4);
+}
+
+enum ClosurePrecision { kClosureFp32 = 0, kClosureFp16Mfma = 1 };
+
+// Everything the closure rates pass needs.
 struct ClosureModel {
     float params[kMlpParams];
     float mu[kMlpIn];
@@ -29,6 +59,8 @@ struct ClosureModel {
     float out_scale[kMlpOut];
     double box_lo[kMlpIn];  // training range of the raw features (fallback test)
     double box_hi[kMlpIn];
+    int precision;          // ClosurePrecision
+    ClosureFp16 h;          // folded operands of the FP16 variant
 };
 
 // tanh(z) = sign(z) (1 - e) / (1 + e), e = exp(-2|z|) in (0, 1]: no overflow,
@@ -125,4 +157,11 @@ __device__ __forceinline__ bool closure_rate(const float *P, const ClosureModel 
     return inside;
 }
 
+}  // namespace sme
+
+namespace sme {
+// the matrix-core kernel loads 8- and 16-byte operand slices of these arrays
+static_assert(offsetof(ClosureModel, h) % 16 == 0 && offsetof(ClosureFp16, w2) % 16 == 0 &&
+                  offsetof(ClosureFp16, w3) % 16 == 0 && sizeof(ClosureFp16::w1[0]) % 16 == 0,
+              "FP16 operand arrays must be 16-byte aligned");
 }  // namespace sme

@@ -23,6 +23,7 @@ SME_MESH_1D, SME_MESH_2D_STRUCT, SME_MESH_2D_TRI = 1, 2, 3
 SME_BC_PERIODIC, SME_BC_EXTRAP, SME_BC_WALL = 0, 1, 2
 BC = {"periodic": SME_BC_PERIODIC, "extrap": SME_BC_EXTRAP, "wall": SME_BC_WALL}
 MAX_LEVEL = 8
+CLOSURE_PRECISIONS = {"fp32": 0, "fp16": 1}  # SME_CLOSURE_FP32, SME_CLOSURE_FP16_MFMA
 
 EXPORTS = [
     "sme_layout", "sme_init", "sme_set_state", "sme_get_state", "sme_eigmax", "sme_step",
@@ -34,7 +35,7 @@ EXPORTS = [
     "sme_batch_last_error", "sme_batch_destroy",
     "sme_mlp_create", "sme_mlp_set_params", "sme_mlp_get_params", "sme_mlp_set_scaling", "sme_mlp_forward",
     "sme_mlp_loss_grad", "sme_mlp_train_step", "sme_mlp_reset_optimizer", "sme_mlp_last_error", "sme_mlp_destroy",
-    "sme_closure_samples", "sme_closure_attach", "sme_closure_out_of_range",
+    "sme_closure_samples", "sme_closure_attach", "sme_closure_attach_ex", "sme_closure_out_of_range",
 ]
 
 
@@ -104,6 +105,7 @@ def _load():
         "sme_mlp_destroy": (None, [vp]),
         "sme_closure_samples": (i, [vp, i64, vp, i64, vp, i64, i64, d, vp, i64, vp, vp, vp]),
         "sme_closure_attach": (i, [vp, vp]),
+        "sme_closure_attach_ex": (i, [vp, vp, i]),
         "sme_closure_out_of_range": (i, [vp, P(i64)]),
     }
     for name, (res, args) in sig.items():
@@ -278,9 +280,16 @@ class Solver:
     def time(self):
         return sme_time(self.ctx)
 
-    def attach_closure(self, mlp):
-        """Attach a trained network (an MLP); None detaches."""
-        _check(_lib.sme_closure_attach(self.ctx, mlp.ctx if mlp is not None else None), self.ctx)
+    def attach_closure(self, mlp, precision="fp32"):
+        """Attach a trained network (an MLP); None detaches.  precision "fp32"
+        (FP32 network) or "fp16" (matrix cores, FP16 operands, FP32 accumulation)."""
+        mode = CLOSURE_PRECISIONS[precision]
+        rc = _lib.sme_closure_attach_ex(self.ctx, mlp.ctx if mlp is not None else None, mode)
+        if rc != 0 and mlp is not None and mlp.ctx:
+            msg = (_lib.sme_mlp_last_error(mlp.ctx) or b"").decode()
+            if msg:
+                raise SmeError(rc, msg)
+        _check(rc, self.ctx)
 
     def out_of_range(self):
         n = ctypes.c_int64()

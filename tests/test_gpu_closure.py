@@ -1,8 +1,9 @@
 """GPU tests of the learned closure: the FP32 network kernels against the FP64
 oracle network (forward, gradient, Adam), the training samples against the
-oracle's level-1 step, the fused level-1 + closure step against the oracle,
-the zero network reducing to plain level 1 bitwise, the out-of-range flag,
-and the gain of a trained closure on held-out seeds."""
+oracle's level-1 step, the level-1 + closure step (FP32 and FP16 matrix-core
+rates) against the oracle, the zero network reducing to plain level 1
+bitwise, the out-of-range flag, and the gain of a trained closure on held-out
+seeds."""
 import numpy as np
 import pytest
 
@@ -177,8 +178,98 @@ def test_closure_step_2d_matches_oracle(env):
     m.close()
 
 
+U16 = 2.0 ** -11  # unit roundoff of FP16
+
+
+def fp16_bound(p, mu, sig, osc, feat, lam=6.0):
+    """Probabilistic error bound of the FP16-operand network per sample and
+    output.  Every matrix operand (normalised input, weight, activation) is
+    rounded once to FP16 (relative error <= u = 2^-11, so <= 2u per product);
+    taking these roundings as independent and zero-mean, Hoeffding's inequality
+    bounds a sum of n such terms by lam * 2u * sqrt(sum of squared terms) except
+    with probability 2 exp(-lam^2 / 2) (3e-8 for lam = 6).  Errors carried in
+    from the previous layer add in quadrature too; tanh' = 1 - a^2; the FP32
+    exp2 / reciprocal add <= 1e-6 per activation; FP32 accumulation is
+    negligible at these sizes."""
+    W1, b1, W2, b2, W3, b3 = omlp.unpack(p.astype(np.float64))
+    x = ((feat.astype(np.float32) - mu) * (np.float32(1.0) / sig)).astype(np.float64)
+    a1 = np.tanh(x @ W1.T + b1)
+    a2 = np.tanh(a1 @ W2.T + b2)
+    e = lam * 2 * U16
+    dz1 = e * np.sqrt((x ** 2) @ (W1 ** 2).T)
+    da1 = (1 - a1 ** 2) * dz1 + lam * U16 * np.abs(a1) + 1e-6
+    dz2 = np.sqrt((da1 ** 2) @ (W2 ** 2).T) + e * np.sqrt((a1 ** 2) @ (W2 ** 2).T)
+    da2 = (1 - a2 ** 2) * dz2 + lam * U16 * np.abs(a2) + 1e-6
+    dy = np.sqrt((da2 ** 2) @ (W3 ** 2).T) + e * np.sqrt((a2 ** 2) @ (W3 ** 2).T)
+    return dy * osc.astype(np.float64)
+
+
+def fp16_rate_check(got, plain, r, bound, dt, fields):
+    """(got - plain step) / dt is the FP16 rate: within the derived bound of the
+    FP64 network's rate, and the bound itself well below the rates."""
+    assert np.max(bound) < 0.05 * np.abs(r).max()
+    for f, rr, bb in zip(fields, r.T, bound.T):
+        d = (got[f] - plain[f]) / dt
+        excess = np.abs(d - rr) - (bb + 1e-6 * np.abs(rr).max())
+        assert np.max(excess) <= 0, (f, np.max(np.abs(d - rr)), np.max(bb))
+
+
+@pytest.mark.parametrize("n", [300, 4099])
+def test_closure_step_1d_fp16(env, n):
+    torch, sme, _ = env
+    p = rand_params(7, scale=1.0)  # activations of order one: the FP16 bound is a small fraction of the rates
+    m, mu, sig, osc = scaled_mlp(sme, p)
+    prob = W.smooth_1d(n=n, level=1, seed=1003)
+    s = sme.Solver(prob)
+    s.attach_closure(m, precision="fp16")
+    s.set_state(prob["q"])
+    dt = 2e-3
+    s.step(dt)
+    got = s.get_state()
+    s.close()
+    plain, _ = orc.from_problem(prob).step(prob["q"], dt)
+    q = prob["q"]
+    f = omlp.features_1d(q[0], q[1], q[2])
+    r = oracle_rate(p, mu, sig, osc, f)
+    np.testing.assert_allclose(got[0], plain[0], rtol=1e-13, atol=0)  # depth untouched
+    fp16_rate_check(got, plain, r, fp16_bound(p, mu, sig, osc, f), dt, (1, 2))
+    m.close()
+
+
+def test_closure_step_2d_fp16(env):
+    torch, sme, _ = env
+    p = rand_params(8, scale=1.0)
+    m, mu, sig, osc = scaled_mlp(sme, p, seed=1)
+    n = 70  # 4900 cells: a ragged last group of 64
+    prob = W.struct_2d(n=n, level=1, L=7.0)
+    rng = np.random.default_rng(4)
+    prob["q"][1:] = prob["q"][0] * rng.uniform(-0.3, 0.3, size=prob["q"][1:].shape)
+    s = sme.Solver(prob)
+    s.attach_closure(m, precision="fp16")
+    s.set_state(prob["q"])
+    dt = 1e-3
+    s.step(dt)
+    got = s.get_state()
+    s.close()
+    plain, _ = orc.from_problem(prob).step(prob["q"], dt)
+    q = prob["q"].reshape(5, n, n)
+
+    def feats(h, a, b, axis):
+        hp, ap, bp = (np.roll(v, -1, axis=axis) for v in (h, a, b))
+        hm, am, bm = (np.roll(v, 1, axis=axis) for v in (h, a, b))
+        return np.stack([h, a, b, hp - h, ap - a, bp - b, h - hm, a - am, b - bm], axis=-1).reshape(-1, 9)
+
+    fx, fy = feats(q[0], q[1], q[2], axis=1), feats(q[0], q[3], q[4], axis=0)
+    rx, ry = oracle_rate(p, mu, sig, osc, fx), oracle_rate(p, mu, sig, osc, fy)
+    np.testing.assert_allclose(got[0], plain[0], rtol=1e-13, atol=0)
+    fp16_rate_check(got, plain, rx, fp16_bound(p, mu, sig, osc, fx), dt, (1, 2))
+    fp16_rate_check(got, plain, ry, fp16_bound(p, mu, sig, osc, fy), dt, (3, 4))
+    m.close()
+
+
 @pytest.mark.parametrize("kind", ["1d", "2d"])
-def test_zero_network_is_plain_level1(env, kind):
+@pytest.mark.parametrize("precision", ["fp32", "fp16"])
+def test_zero_network_is_plain_level1(env, kind, precision):
     torch, sme, _ = env
     prob = W.smooth_1d(n=500, level=1, seed=1010) if kind == "1d" else W.struct_2d(n=90, level=1)
     out = []
@@ -186,7 +277,7 @@ def test_zero_network_is_plain_level1(env, kind):
         s = sme.Solver(prob)
         if attach:
             m = sme.MLP(np.zeros(omlp.NPARAM, dtype=np.float32))
-            s.attach_closure(m)
+            s.attach_closure(m, precision=precision)
         s.set_state(prob["q"])
         s.run(40)
         out.append(s.get_state())
@@ -194,7 +285,8 @@ def test_zero_network_is_plain_level1(env, kind):
     assert np.array_equal(out[0], out[1])
 
 
-def test_out_of_range_flag(env):
+@pytest.mark.parametrize("precision", ["fp32", "fp16"])
+def test_out_of_range_flag(env, precision):
     torch, sme, _ = env
     m = sme.MLP(np.zeros(omlp.NPARAM, dtype=np.float32))
     prob = W.smooth_1d(n=256, level=1, seed=1011)
@@ -204,7 +296,7 @@ def test_out_of_range_flag(env):
     hi[0] = 1.0
     m.set_scaling(np.zeros(9), np.ones(9), np.ones(2), lo, hi)
     s = sme.Solver(prob)
-    s.attach_closure(m)
+    s.attach_closure(m, precision=precision)
     s.set_state(prob["q"])
     s.run(3)
     n_out = s.out_of_range()
@@ -212,7 +304,7 @@ def test_out_of_range_flag(env):
     # a network that is not trusted anywhere leaves plain level 1
     m2 = sme.MLP(rand_params(9))
     m2.set_scaling(np.zeros(9), np.ones(9), np.ones(2), np.full(9, 1e3), np.full(9, 2e3))
-    s.attach_closure(m2)
+    s.attach_closure(m2, precision=precision)
     s.set_state(prob["q"])
     s.run(10)
     off = s.get_state()
@@ -225,7 +317,7 @@ def test_out_of_range_flag(env):
     m2.close()
     hi[0] = 1e3
     m.set_scaling(np.zeros(9), np.ones(9), np.ones(2), lo, hi)
-    s.attach_closure(m)
+    s.attach_closure(m, precision=precision)
     s.set_state(prob["q"])
     s.run(3)
     assert s.out_of_range() == 0
@@ -251,10 +343,11 @@ def test_trained_closure_gain_on_held_out_seeds(env):
         ref = s8.get_state()
         s8.close()
         res = {}
-        for name, net in (("plain", sme.MLP(np.zeros(omlp.NPARAM, dtype=np.float32))), ("closure", mlp)):
+        zero = sme.MLP(np.zeros(omlp.NPARAM, dtype=np.float32))
+        for name, net, prec in (("plain", zero, "fp32"), ("closure", mlp, "fp32"), ("closure16", mlp, "fp16")):
             p1 = dict(p8, level=1, q=p8["q"][:3].copy())
             s1 = sme.Solver(p1)
-            s1.attach_closure(net)
+            s1.attach_closure(net, precision=prec)
             s1.set_state(p1["q"])
             s1.run(10 ** 6, t_end=T)
             q1 = s1.get_state()
@@ -263,6 +356,9 @@ def test_trained_closure_gain_on_held_out_seeds(env):
             e = closure.relative_l1(q1, ref[:3], fields=(0, 1))
             res[name] = e
         g = (res["closure"][0] + res["closure"][1]) / (res["plain"][0] + res["plain"][1])
-        print(f"seed {seed}: plain {res['plain']} closure {res['closure']} gain {g:.3f}", flush=True)
-        gains.append(g)
-    assert np.mean(gains) < 1.0
+        g16 = (res["closure16"][0] + res["closure16"][1]) / (res["plain"][0] + res["plain"][1])
+        print(f"seed {seed}: plain {res['plain']} closure {res['closure']} gain {g:.3f} (fp16 {g16:.3f})", flush=True)
+        gains.append((g, g16))
+    gains = np.array(gains)
+    assert gains[:, 0].mean() < 1.0
+    assert gains[:, 1].mean() < 1.0
