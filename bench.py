@@ -248,7 +248,9 @@ def bench_closure(args, wl, torch, sme, workloads):
     T, n8 = s8.time()
     ref = s8.get_state()
     s8.close()
-    q1_init = closure._project_state(p8["q"], p8)
+    # initial states from device memory (no pageable host upload inside the runs)
+    q1_init = torch.from_numpy(closure._project_state(p8["q"], p8)).cuda()
+    torch.cuda.synchronize()
     results = {}
     for name, net, prec in (("closure_fp16", mlp, "fp16"), ("closure_fp32", mlp, "fp32"), ("plain", None, None)):
         p1 = dict(p8, level=1, q=q1_init)

@@ -124,8 +124,10 @@ int sme_step(sme_ctx *ctx, double dt, double *dt_used);
 
 /* n_steps CFL steps, queued as replays of a captured HIP graph.  t_end > 0
  * stops the simulated time at t_end: the last step is shortened, and the call
- * stops queueing steps once the device clock has reached t_end (it looks every
- * 60 steps, so up to 60 steps after that are no-ops).  If t_out / steps_done are not NULL the stream is synchronised
+ * stops queueing steps once the device clock has reached t_end.  It reads the
+ * clock two graphs (12 steps) behind the newest queued one, so the call blocks
+ * while the device works through its queue, and up to 12 steps after t_end are
+ * no-ops (a copy of the state each).  If t_out / steps_done are not NULL the stream is synchronised
  * and the simulated time since sme_set_state and the number of steps that
  * advanced the state are returned; SME_ENONPHYS is returned if a step produced
  * h <= 0 or a non-finite value (the state is then not usable). */

@@ -24,11 +24,14 @@ FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
          # keep constant materialisation next to its use: hoisting hundreds of
          # FP64 tensor literals out of the row loop only spills them
          "-mllvm", "-disable-machine-licm"]
+# per-source extras: matrix-core results in ordinary VGPRs, so the activations
+# read them without v_accvgpr_read copies (the unified register file has room)
+EXTRA = {"k_closure.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
 
 def _compile(src):
     out = os.path.join(OBJ, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", out]
+    cmd = [HIPCC] + FLAGS + EXTRA.get(src, []) + ["-c", os.path.join(CSRC, src), "-o", out]
     if src.endswith(".cpp"):
         cmd[1:1] = ["-x", "hip"]
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -48,16 +48,16 @@ __device__ __forceinline__ void nb_normal(const StepArgs &a, int i, int j, int d
 // grid = nblk blocks per direction; blocks [0, nblk) do x, [nblk, 2 nblk) do y
 __global__ __launch_bounds__(kBlock) void k_closure_rates_valu(StepArgs a, unsigned nblk)
 {
+    if (!(step_dt(a) > 0.0)) return;  // a step past the end time reads no rates
     __shared__ float P[kMlpParams];
     mlp_stage(a.closure->params, P);
     const int dir = blockIdx.x >= nblk ? 1 : 0;
     const int64_t cell = (int64_t)(blockIdx.x - dir * nblk) * kBlock + threadIdx.x;
     float2 *rates = reinterpret_cast<float2 *>(const_cast<float *>(a.rates)) + dir * a.stride;
-    const bool live = step_dt(a) > 0.0;  // a step past the end time changes nothing
     unsigned out = 0;
     if (cell < a.ncells) {
         float2 r = make_float2(0.0f, 0.0f);
-        if (live) {
+        {
             const int i = (int)(cell % a.nx), j = (int)(cell / a.nx);
             const int blk = dir ? 3 : 1;  // level 1: fields h, qx_0, qx_1, qy_0, qy_1
             const double h = a.q[cell];
@@ -124,6 +124,7 @@ constexpr int kGroup = 64;  // samples per wave and pass
 __global__ __launch_bounds__(kBlock) void k_closure_rates_mfma(StepArgs a, int64_t per_dir, int64_t ngroups)
 {
     __shared__ __attribute__((aligned(16))) _Float16 X[kBlock / kWave][kGroup][kMlpInPad];
+    if (!(step_dt(a) > 0.0)) return;  // a step past the end time reads no rates
     const ClosureFp16 &H = a.closure->h;
     const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x >> 6;
     const int g = lane >> 4, col = lane & 15;
@@ -146,7 +147,6 @@ __global__ __launch_bounds__(kBlock) void k_closure_rates_mfma(StepArgs a, int64
 #pragma unroll
     for (int r = 0; r < 4; ++r) c3[r] = g == 0 ? H.c3[r] : 0.0f;
     const float os0 = a.closure->out_scale[0], os1 = a.closure->out_scale[1];
-    const bool live = step_dt(a) > 0.0;  // a step past the end time changes nothing
     const int64_t nwaves = (int64_t)gridDim.x * (kBlock / kWave);
     unsigned out = 0;
     for (int64_t grp = (int64_t)blockIdx.x * (kBlock / kWave) + wv; grp < ngroups; grp += nwaves) {
@@ -160,7 +160,7 @@ __global__ __launch_bounds__(kBlock) void k_closure_rates_mfma(StepArgs a, int64
 #pragma unroll
             for (int k = 0; k < kMlpIn; ++k) x[k] = 0.0f;
             bool inside = false;
-            if (cell < a.ncells && live) {
+            if (cell < a.ncells) {
                 inside = sample_features(a, cell, dir, x);
                 out += inside ? 0u : 1u;
             }
@@ -175,27 +175,46 @@ __global__ __launch_bounds__(kBlock) void k_closure_rates_mfma(StepArgs a, int64
             // keep: the in-box flag of every sample of the group
             const unsigned long long inmask = __ballot(inside);
             __builtin_amdgcn_wave_barrier();
+            // two tiles at a time, interleaved layer by layer: the matrix
+            // cores work on one tile while the activations of the other run
 #pragma unroll 1
-            for (int t = 0; t < kGroup / 16; ++t) {
-                const half4 xb = *reinterpret_cast<const half4 *>(&X[wv][16 * t + col][4 * g]);
-                float4v u1[4];
+            for (int t = 0; t < kGroup / 16; t += 2) {
+                const half4 xa = *reinterpret_cast<const half4 *>(&X[wv][16 * t + col][4 * g]);
+                const half4 xb = *reinterpret_cast<const half4 *>(&X[wv][16 * t + 16 + col][4 * g]);
+                float4v ua[4], ub[4], va[4], vb[4];
 #pragma unroll
-                for (int mt = 0; mt < 4; ++mt) u1[mt] = __builtin_amdgcn_mfma_f32_16x16x16f16(w1[mt], xb, c1[mt], 0, 0, 0);
-                const half8 s10 = act_pair(u1[0], u1[1]), s11 = act_pair(u1[2], u1[3]);
-                float4v u2[4];
+                for (int mt = 0; mt < 4; ++mt) ua[mt] = __builtin_amdgcn_mfma_f32_16x16x16f16(w1[mt], xa, c1[mt], 0, 0, 0);
+#pragma unroll
+                for (int mt = 0; mt < 4; ++mt) ub[mt] = __builtin_amdgcn_mfma_f32_16x16x16f16(w1[mt], xb, c1[mt], 0, 0, 0);
+                const half8 sa0 = act_pair(ua[0], ua[1]), sa1 = act_pair(ua[2], ua[3]);
 #pragma unroll
                 for (int mt = 0; mt < 4; ++mt) {
-                    u2[mt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(w2[mt][0], s10, c2[mt], 0, 0, 0);
-                    u2[mt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(w2[mt][1], s11, u2[mt], 0, 0, 0);
+                    va[mt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(w2[mt][0], sa0, c2[mt], 0, 0, 0);
+                    va[mt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(w2[mt][1], sa1, va[mt], 0, 0, 0);
                 }
-                const half8 s20 = act_pair(u2[0], u2[1]), s21 = act_pair(u2[2], u2[3]);
-                float4v y = __builtin_amdgcn_mfma_f32_16x16x32_f16(w3[0], s20, c3, 0, 0, 0);
-                y = __builtin_amdgcn_mfma_f32_16x16x32_f16(w3[1], s21, y, 0, 0, 0);
-                const int smp = 16 * t + col;
-                const int64_t c = cell0 + smp;
-                if (g == 0 && c < a.ncells) {
-                    const bool ok = ((inmask >> smp) & 1ull) != 0;
-                    rates[c] = ok ? make_float2(os0 * y[0], os1 * y[1]) : make_float2(0.0f, 0.0f);
+                const half8 sb0 = act_pair(ub[0], ub[1]), sb1 = act_pair(ub[2], ub[3]);
+#pragma unroll
+                for (int mt = 0; mt < 4; ++mt) {
+                    vb[mt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(w2[mt][0], sb0, c2[mt], 0, 0, 0);
+                    vb[mt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(w2[mt][1], sb1, vb[mt], 0, 0, 0);
+                }
+                const half8 ta0 = act_pair(va[0], va[1]), ta1 = act_pair(va[2], va[3]);
+                float4v ya = __builtin_amdgcn_mfma_f32_16x16x32_f16(w3[0], ta0, c3, 0, 0, 0);
+                ya = __builtin_amdgcn_mfma_f32_16x16x32_f16(w3[1], ta1, ya, 0, 0, 0);
+                const half8 tb0 = act_pair(vb[0], vb[1]), tb1 = act_pair(vb[2], vb[3]);
+                float4v yb = __builtin_amdgcn_mfma_f32_16x16x32_f16(w3[0], tb0, c3, 0, 0, 0);
+                yb = __builtin_amdgcn_mfma_f32_16x16x32_f16(w3[1], tb1, yb, 0, 0, 0);
+                if (g == 0) {
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const float4v &y = h ? yb : ya;
+                        const int smp = 16 * (t + h) + col;
+                        const int64_t c = cell0 + smp;
+                        if (c < a.ncells) {
+                            const bool ok = ((inmask >> smp) & 1ull) != 0;
+                            rates[c] = ok ? make_float2(os0 * y[0], os1 * y[1]) : make_float2(0.0f, 0.0f);
+                        }
+                    }
                 }
             }
             __builtin_amdgcn_wave_barrier();

@@ -21,6 +21,10 @@ __global__ __launch_bounds__(kBlock) void k_step_1d(StepArgs a)
     constexpr int n = N + 1;
     const double dt = step_dt(a);
     if (blockIdx.x == 0 && threadIdx.x == 0) slot_update(a, dt);
+    if (dt == 0.0) {
+        noop_step(a, N + 2);
+        return;
+    }
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = (blockIdx.x * kBlock + threadIdx.x) >> 6;
     const int x0 = wave * kOut;

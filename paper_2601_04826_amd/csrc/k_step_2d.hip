@@ -14,6 +14,10 @@ __global__ __launch_bounds__(kBlock) void k_step_2d(StepArgs a)
 {
     const double dt = step_dt(a);
     if (blockIdx.x == 0 && threadIdx.x == 0) slot_update(a, dt);
+    if (dt == 0.0) {
+        noop_step(a, 2 * N + 3);
+        return;
+    }
     const int nsx = (a.nx + kOut - 1) / kOut;
     const int nsy = (a.ny + a.rows - 1) / a.rows;
     // XCD-aware order: blocks are dealt round-robin to the kXcd dies, so block b

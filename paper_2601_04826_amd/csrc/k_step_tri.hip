@@ -32,6 +32,10 @@ __global__ __launch_bounds__(kBlock) void k_step_tri(StepArgs a)
     constexpr int nf = 2 * n + 1;
     const double dt = step_dt(a);
     if (blockIdx.x == 0 && threadIdx.x == 0) slot_update(a, dt);
+    if (dt == 0.0) {
+        noop_step(a, nf);
+        return;
+    }
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     double r = 0.0;
     if (i < a.ncells) {

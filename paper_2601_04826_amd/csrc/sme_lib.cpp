@@ -62,6 +62,8 @@ struct sme_ctx {
     unsigned long long *oor = nullptr;  // cells that left the closure's training range
     float *rates = nullptr;             // closure rates of the current state (2 or 4 per cell)
     int closure_mode = 0;               // ClosurePrecision of the attached network
+    double *t_host = nullptr;           // pinned: simulated time after the latest graph with an end time
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};  // completion of the last graphs of a run
     int cus = 256;                      // compute units of the device
     int cur = 0;   // which q[] holds the state
     int sa = 0;    // slot describing the current state
@@ -363,6 +365,9 @@ int get_graph(sme_ctx *c, double t_end, hipGraphExec_t *out)
     HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
     hipError_t le = hipSuccess;
     for (int k = 0; k < kGraphSteps && le == hipSuccess; ++k) le = launch_one_step(c, 0.0, t_end);
+    // with an end time the graph also reports the simulated time to the host
+    if (le == hipSuccess && t_end > 0.0)
+        le = hipMemcpyAsync(c->t_host, &c->slots[sa0].t, sizeof(double), hipMemcpyDeviceToHost, c->stream);
     hipGraph_t graph = nullptr;
     hipError_t ee = hipStreamEndCapture(c->stream, &graph);
     c->cur = cur0;
@@ -642,24 +647,32 @@ int sme_run(sme_ctx *c, int64_t n_steps, double t_end, double *t_out, int64_t *s
     const double te = t_end > 0 ? t_end : 0.0;
     int64_t left = n_steps;
     const bool use_graphs = getenv("SME_NO_GRAPH") == nullptr;
-    // with an end time, look at the device clock every kCheckChunks graphs and
-    // stop once it has reached t_end (the steps after that would be no-ops)
-    constexpr int kCheckChunks = 10;
-    int chunks = 0;
+    // With an end time every graph copies the device clock to pinned host
+    // memory.  After queueing graph k the host waits for graph k - 2 and stops
+    // once its clock has reached t_end: the device always has queued work, and
+    // at most two graphs of no-op steps (dt = 0, a plain copy) follow the end.
+    if (use_graphs && te > 0.0 && left >= kGraphSteps && !c->t_host) {
+        HIPCHK(c, hipHostMalloc((void **)&c->t_host, sizeof(double), hipHostMallocDefault));
+        for (auto &e : c->ev) HIPCHK(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    }
+    int64_t k = 0;
     while (use_graphs && left >= kGraphSteps) {
         hipGraphExec_t ex;
         int r = get_graph(c, te, &ex);
         if (r) return r;
         HIPCHK(c, hipGraphLaunch(ex, c->stream));
         left -= kGraphSteps;  // after six steps cur and slot are back where they started
-        if (te > 0.0 && ++chunks % kCheckChunks == 0) {
-            Slot s;
-            int rr = read_slot(c, &s, nullptr);
-            if (rr) return rr;
-            if (s.t >= te) {
-                left = 0;
-                break;
+        if (te > 0.0) {
+            HIPCHK(c, hipEventRecord(c->ev[k % 3], c->stream));
+            if (k >= 2) {
+                // stream order: every earlier copy to t_host has landed, later ones only raise it
+                HIPCHK(c, hipEventSynchronize(c->ev[(k - 2) % 3]));
+                if (*(volatile double *)c->t_host >= te) {
+                    left = 0;
+                    break;
+                }
             }
+            ++k;
         }
     }
     while (left-- > 0) HIPCHK(c, launch_one_step(c, 0.0, te));
@@ -794,6 +807,9 @@ void sme_destroy(sme_ctx *c)
     (void)hipFree(c->closure);
     (void)hipFree(c->oor);
     (void)hipFree(c->rates);
+    if (c->t_host) (void)hipHostFree(c->t_host);
+    for (auto &e : c->ev)
+        if (e) (void)hipEventDestroy(e);
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }

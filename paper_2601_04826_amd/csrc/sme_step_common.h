@@ -60,6 +60,23 @@ __device__ __forceinline__ void slot_update(const StepArgs &a, double dt)
     a.slots[a.sc].lbits = 0ull;
 }
 
+// A step past the end time (dt = 0) leaves the state as it is: every thread of
+// the grid copies its share of Q^n to Q^{n+1}, and one lane carries the CFL
+// ratio and largest wave speed over to the next slot (no block reduces).
+// dt is the same for the whole grid, so either every block takes this path
+// or none does.
+__device__ __forceinline__ void noop_step(const StepArgs &a, int nf)
+{
+    const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int f = 0; f < nf; ++f)
+        for (int64_t i = t0; i < a.ncells; i += nth) a.qn[f * a.stride + i] = a.q[f * a.stride + i];
+    if (t0 == 0) {
+        a.slots[a.sb].rbits = a.slots[a.sa].rbits;
+        a.slots[a.sb].lbits = a.slots[a.sa].lbits;
+    }
+}
+
 __device__ __forceinline__ double wave_max(double v)
 {
 #pragma unroll

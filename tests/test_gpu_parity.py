@@ -242,6 +242,34 @@ def test_t_end_clamps_time(sme):
     s.close()
 
 
+@pytest.mark.parametrize("kind", ["1d", "2d", "tri"])
+def test_steps_past_end_time_keep_state(sme, kind):
+    """Steps queued after the clock reached t_end copy the state and carry the
+    CFL ratio over: continuing afterwards gives bitwise the same states as a
+    run that queued exactly the steps it needed."""
+    if kind == "1d":
+        p = W.dam_break_1d()
+    elif kind == "2d":
+        p = W.struct_2d(n=100, level=2)
+    else:
+        p = W.tri_2d(npts=3000, level=2)
+    T = 0.02
+    a = sme.Solver(p)
+    a.set_state(p["q"])
+    ta, na = a.run(100000, t_end=T)  # many graphs of no-op steps queued after T
+    b = sme.Solver(p)
+    b.set_state(p["q"])
+    tb, nb = b.run(na, t_end=T)
+    assert (ta, na) == (tb, nb) and abs(ta - T) <= 1e-15
+    assert np.array_equal(a.get_state(), b.get_state())
+    a.run(40)
+    b.run(40)
+    assert a.time() == b.time()
+    assert np.array_equal(a.get_state(), b.get_state())
+    a.close()
+    b.close()
+
+
 def test_nonphysical_state_reported(sme):
     p = W.dam_break_1d(n=100)
     p["q"][0, 40] = -0.5
