@@ -79,10 +79,10 @@ typedef float float4v __attribute__((ext_vector_type(4)));
 
 // raw features of sample (cell, dir) and whether they lie in the training box;
 // x = normalised features (FP32, same arithmetic as the FP32 variant)
-__device__ __forceinline__ bool sample_features(const StepArgs &a, int64_t cell, int dir, float *x)
+__device__ __forceinline__ bool sample_features(const StepArgs &a, int i, int j, int dir, float *x)
 {
     const ClosureModel *M = a.closure;
-    const int i = (int)(cell % a.nx), j = (int)(cell / a.nx);
+    const int64_t cell = (int64_t)j * a.nx + i;
     const int blk = dir ? 3 : 1;
     const double h = a.q[cell];
     const double q0 = a.q[blk * a.stride + cell], q1 = a.q[(blk + 1) * a.stride + cell];
@@ -119,23 +119,32 @@ __device__ __forceinline__ half8 act_pair(const float4v &lo, const float4v &hi)
 
 constexpr int kGroup = 64;  // samples per wave and pass
 
-// groups of 64 consecutive cells, direction-major: group k covers direction
-// k / per_dir; waves stride over the groups
-__global__ __launch_bounds__(kBlock) void k_closure_rates_mfma(StepArgs a, int64_t per_dir, int64_t ngroups)
+// A group is 64 consecutive cells of one row and one direction: group k has
+// direction k / per_dir, row r / chunks and columns 64 (r % chunks) + lane
+// with r = k % per_dir and per_dir = rows x chunks, so row and first column
+// are the same for the whole wave.  Waves stride over the groups.
+__global__ __launch_bounds__(kBlock) void k_closure_rates_mfma(StepArgs a, int chunks, int per_dir, int ngroups)
 {
     __shared__ __attribute__((aligned(16))) _Float16 X[kBlock / kWave][kGroup][kMlpInPad];
     if (!(step_dt(a) > 0.0)) return;  // a step past the end time reads no rates
     const ClosureFp16 &H = a.closure->h;
     const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x >> 6;
     const int g = lane >> 4, col = lane & 15;
+    // second-layer operand slices, staged once per block in the order the
+    // lanes read them (16 contiguous bytes per lane: no bank conflicts); kept
+    // out of registers, which leaves room for three waves per SIMD
+    __shared__ __attribute__((aligned(16))) half8 W2s[4][2][kWave];
+    for (int idx = threadIdx.x; idx < 4 * 2 * kWave; idx += kBlock) {
+        const int mt = idx / (2 * kWave), kc = (idx / kWave) % 2, l = idx % kWave;
+        W2s[mt][kc][l] = *reinterpret_cast<const half8 *>(&H.w2[16 * mt + (l & 15)][32 * kc + 8 * (l >> 4)]);
+    }
+    __syncthreads();
     half4 w1[4];
-    half8 w2[4][2], w3[2];
+    half8 w3[2];
     float4v c1[4], c2[4], c3;
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt) {
         w1[mt] = *reinterpret_cast<const half4 *>(&H.w1[16 * mt + col][4 * g]);
-#pragma unroll
-        for (int kc = 0; kc < 2; ++kc) w2[mt][kc] = *reinterpret_cast<const half8 *>(&H.w2[16 * mt + col][32 * kc + 8 * g]);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             c1[mt][r] = H.c1[16 * mt + 4 * g + r];
@@ -147,21 +156,24 @@ __global__ __launch_bounds__(kBlock) void k_closure_rates_mfma(StepArgs a, int64
 #pragma unroll
     for (int r = 0; r < 4; ++r) c3[r] = g == 0 ? H.c3[r] : 0.0f;
     const float os0 = a.closure->out_scale[0], os1 = a.closure->out_scale[1];
-    const int64_t nwaves = (int64_t)gridDim.x * (kBlock / kWave);
+    const int nwaves = (int)gridDim.x * (kBlock / kWave);
     unsigned out = 0;
-    for (int64_t grp = (int64_t)blockIdx.x * (kBlock / kWave) + wv; grp < ngroups; grp += nwaves) {
+    for (int grp = (int)blockIdx.x * (kBlock / kWave) + wv; grp < ngroups; grp += nwaves) {
         const int dir = grp >= per_dir ? 1 : 0;
-        const int64_t cell0 = (grp - dir * per_dir) * kGroup;
-        float2 *rates = reinterpret_cast<float2 *>(const_cast<float *>(a.rates)) + dir * a.stride;
+        const int r = grp - dir * per_dir;
+        const int j = r / chunks;
+        const int i0 = (r - j * chunks) * kGroup;
+        float2 *rates = reinterpret_cast<float2 *>(const_cast<float *>(a.rates)) + dir * a.stride +
+                        ((int64_t)j * a.nx + i0);
+        const int ncol = min(kGroup, a.nx - i0);  // columns of this group inside the grid
         // features: one sample per lane
         {
-            const int64_t cell = cell0 + lane;
             float x[kMlpIn];
 #pragma unroll
             for (int k = 0; k < kMlpIn; ++k) x[k] = 0.0f;
             bool inside = false;
-            if (cell < a.ncells) {
-                inside = sample_features(a, cell, dir, x);
+            if (lane < ncol) {
+                inside = sample_features(a, i0 + lane, j, dir, x);
                 out += inside ? 0u : 1u;
             }
             half8 lo, hi;
@@ -189,14 +201,14 @@ __global__ __launch_bounds__(kBlock) void k_closure_rates_mfma(StepArgs a, int64
                 const half8 sa0 = act_pair(ua[0], ua[1]), sa1 = act_pair(ua[2], ua[3]);
 #pragma unroll
                 for (int mt = 0; mt < 4; ++mt) {
-                    va[mt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(w2[mt][0], sa0, c2[mt], 0, 0, 0);
-                    va[mt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(w2[mt][1], sa1, va[mt], 0, 0, 0);
+                    va[mt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(W2s[mt][0][lane], sa0, c2[mt], 0, 0, 0);
+                    va[mt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(W2s[mt][1][lane], sa1, va[mt], 0, 0, 0);
                 }
                 const half8 sb0 = act_pair(ub[0], ub[1]), sb1 = act_pair(ub[2], ub[3]);
 #pragma unroll
                 for (int mt = 0; mt < 4; ++mt) {
-                    vb[mt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(w2[mt][0], sb0, c2[mt], 0, 0, 0);
-                    vb[mt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(w2[mt][1], sb1, vb[mt], 0, 0, 0);
+                    vb[mt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(W2s[mt][0][lane], sb0, c2[mt], 0, 0, 0);
+                    vb[mt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(W2s[mt][1][lane], sb1, vb[mt], 0, 0, 0);
                 }
                 const half8 ta0 = act_pair(va[0], va[1]), ta1 = act_pair(va[2], va[3]);
                 float4v ya = __builtin_amdgcn_mfma_f32_16x16x32_f16(w3[0], ta0, c3, 0, 0, 0);
@@ -209,10 +221,9 @@ __global__ __launch_bounds__(kBlock) void k_closure_rates_mfma(StepArgs a, int64
                     for (int h = 0; h < 2; ++h) {
                         const float4v &y = h ? yb : ya;
                         const int smp = 16 * (t + h) + col;
-                        const int64_t c = cell0 + smp;
-                        if (c < a.ncells) {
+                        if (smp < ncol) {
                             const bool ok = ((inmask >> smp) & 1ull) != 0;
-                            rates[c] = ok ? make_float2(os0 * y[0], os1 * y[1]) : make_float2(0.0f, 0.0f);
+                            rates[smp] = ok ? make_float2(os0 * y[0], os1 * y[1]) : make_float2(0.0f, 0.0f);
                         }
                     }
                 }
@@ -229,12 +240,15 @@ hipError_t launch_closure_rates(const StepArgs &a, int dims, int mode, int cus, 
 {
     if (dims < 1 || dims > 2) return hipErrorInvalidValue;
     if (mode == kClosureFp16Mfma) {
-        const int64_t per_dir = (a.ncells + kGroup - 1) / kGroup;
+        const int64_t chunks = (a.nx + kGroup - 1) / kGroup;
+        const int64_t per_dir = chunks * a.ny;
         const int64_t ngroups = per_dir * dims;
+        if (ngroups > INT32_MAX) return hipErrorInvalidValue;
         // enough blocks to fill every SIMD several times; waves stride over the rest
         const int64_t want = (ngroups + kBlock / kWave - 1) / (kBlock / kWave);
         const unsigned grid = (unsigned)std::min<int64_t>(want, (int64_t)cus * 8);
-        hipLaunchKernelGGL(k_closure_rates_mfma, dim3(grid), dim3(kBlock), 0, s, a, per_dir, ngroups);
+        hipLaunchKernelGGL(k_closure_rates_mfma, dim3(grid), dim3(kBlock), 0, s, a, (int)chunks, (int)per_dir,
+                           (int)ngroups);
         return hipGetLastError();
     }
     if (mode != kClosureFp32) return hipErrorInvalidValue;
