@@ -142,7 +142,9 @@ def main():
 
     stream = torch.cuda.Stream()
     solver = sme.Solver(problem, stream=stream.cuda_stream)
-    solver.set_state(problem["q"])
+    q0 = torch.from_numpy(problem["q"]).cuda()  # initial state from device memory
+    torch.cuda.synchronize()
+    solver.set_state(q0)
     torch.cuda.synchronize()
     solver.run(args.warmup, sync=True)
     torch.cuda.synchronize()
