@@ -20,6 +20,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -44,7 +46,7 @@ WORKLOADS = {
                               name="struct_2d_4096x4096_level2_periodic"),
     "batch_512": dict(gen="batch", args={}, kernel="k_batch_step",
                       name="batch_512_grids_side64-512_levels1-4_walls"),
-    "closure_2048": dict(gen="closure", args={}, kernel="k_step_2d<1,closure>",
+    "closure_2048": dict(gen="closure", args={}, kernel="k_closure_rates_mfma",
                          name="closure_level1_vs_level8_2048x2048_periodic"),
 }
 
@@ -208,6 +210,26 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+def _project_level(q8, p8, lev):
+    """(h, moments 0..lev of each direction) of a level-8 2D state."""
+    n8 = p8["level"] + 1
+    return np.ascontiguousarray(np.concatenate([q8[:1], q8[1:2 + lev], q8[1 + n8:2 + n8 + lev]]))
+
+
+def _state_hhu(torch, solver):
+    """Fields 0 and 1 (h and h u, at the same place at every level) of the
+    current state, kept in device memory."""
+    full = torch.empty((solver.nf, solver.ncells), dtype=torch.float64, device="cuda")
+    solver.get_state(full)
+    torch.cuda.synchronize()
+    return full[:2].clone()
+
+
+def _rel_l1(q, ref):
+    """E_x = sum_i |x_i - x_i^ref| / sum_i |x_i^ref| for x = h, h u (equal cells), on the device."""
+    return [float((q[f] - ref[f]).abs().sum() / ref[f].abs().sum()) for f in (0, 1)]
+
+
 def bench_closure(args, wl, torch, sme, workloads):
     """Learned closure: train on level-8 runs the solver generates, then run
     level 1 + closure and plain level 8 (and plain level 1) on a 2048^2 periodic
@@ -237,9 +259,11 @@ def bench_closure(args, wl, torch, sme, workloads):
 
     # level 8 reference: args.steps steps fix the end time
     s8 = sme.Solver(p8, stream=st.cuda_stream)
-    s8.set_state(p8["q"])
+    q8_init = torch.from_numpy(p8["q"]).cuda()  # initial states from device memory
+    torch.cuda.synchronize()
+    s8.set_state(q8_init)
     s8.run(3)
-    s8.set_state(p8["q"])
+    s8.set_state(q8_init)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(st)
@@ -248,9 +272,9 @@ def bench_closure(args, wl, torch, sme, workloads):
     torch.cuda.synchronize()
     ms8 = e0.elapsed_time(e1)
     T, n8 = s8.time()
-    ref = s8.get_state()
+    ref = _state_hhu(torch, s8)
     s8.close()
-    # initial states from device memory (no pageable host upload inside the runs)
+    del q8_init
     q1_init = torch.from_numpy(closure._project_state(p8["q"], p8)).cuda()
     torch.cuda.synchronize()
     results = {}
@@ -269,12 +293,37 @@ def bench_closure(args, wl, torch, sme, workloads):
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1)
         t1_, n1 = s1.time()
-        q1 = s1.get_state()
+        q1 = _state_hhu(torch, s1)
         oor = s1.out_of_range() if net is not None else 0
         s1.close()
-        lifted = closure._lift_state(q1, p8)
-        err = closure.relative_l1(lifted, ref, fields=(0, 1))
+        err = _rel_l1(q1, ref)
         results[name] = dict(ms=ms, steps=n1, t=t1_, err_h=err[0], err_hu=err[1], out_of_range=oor)
+    # equal-error comparison: the smallest plain level whose error is within
+    # the closure's, and the closure's speedup over it at the same end time
+    tgt = results["closure_" + args.closure_precision]
+    equal = None
+    for lev in range(2, 8):
+        pN = workloads.smooth_2d(n=2048, level=8, seed=2000)
+        qN = torch.from_numpy(_project_level(pN["q"], pN, lev)).cuda()
+        pN = dict(pN, level=lev, q=None)
+        sN = sme.Solver(pN, stream=st.cuda_stream)
+        sN.set_state(qN)
+        sN.run(3)
+        sN.set_state(qN)
+        torch.cuda.synchronize()
+        e0.record(st)
+        sN.run(100 * args.steps, t_end=T, sync=False)
+        e1.record(st)
+        torch.cuda.synchronize()
+        msN = e0.elapsed_time(e1)
+        qNf = _state_hhu(torch, sN)
+        sN.close()
+        errN = _rel_l1(qNf, ref)
+        print(f"[bench] plain level {lev}: {msN:.1f} ms, err_h {errN[0]:.3e}, err_hu {errN[1]:.3e}",
+              file=sys.stderr, flush=True)
+        if errN[0] + errN[1] <= tgt["err_h"] + tgt["err_hu"]:
+            equal = dict(level=lev, ms=msN, err_h=errN[0], err_hu=errN[1], speedup_closure_over_it=msN / tgt["ms"])
+            break
     pl = results["plain"]
     for r in results.values():
         r["speedup_vs_level8_same_time"] = ms8 / r["ms"]
@@ -303,6 +352,7 @@ def bench_closure(args, wl, torch, sme, workloads):
                      "alg_bytes_per_launch": alg, "avg_launch_us": c["ms"] * 1e3 / max(1, c["steps"]),
                      "note": "network flops over the whole level-1 + closure step time"},
         "closure": {"level8_ms": ms8, "level8_steps": n8, "level8_cell_updates_per_s": cells * n8 / (ms8 * 1e-3),
+                    "smallest_plain_level_at_closure_error": equal,
                     "level8_err_budget": {"err_h": pl["err_h"], "err_hu": pl["err_hu"]}, **results},
         "cpu_baseline": None,
     }
