@@ -70,7 +70,8 @@ __global__ __launch_bounds__(kBlock) void k_batch_step(BatchArgs B)
         default: break;
         }
         r = wave_max(r);
-        if (lane == 0 && r > 0.0) atomicMax(&a.slots[a.sb].rbits, (unsigned long long)__double_as_longlong(r));
+        if (lane == 0 && r > 0.0)
+            atomicMax(&a.slots[a.sb].r[blockIdx.x % kRatioWords].bits, (unsigned long long)__double_as_longlong(r));
     }
 }
 

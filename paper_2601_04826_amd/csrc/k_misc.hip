@@ -1,6 +1,8 @@
 // k_misc.hip -- eigenvalue-bound reduction, slot reset and permutation kernels.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "sme_step_common.h"
 
 namespace sme {
@@ -11,13 +13,15 @@ namespace {
 
 // ----------------------------------------------------------------------------
 // Eigenvalue bound over the current state: max CFL ratio and max lam into slot sa.
+// A grid-stride loop over a few blocks per compute unit: one atomic per block
+// and quantity, so the atomics on the two slot words stay few.
 template <int N, int KIND>
 __global__ __launch_bounds__(kBlock) void k_eig(StepArgs a)
 {
     constexpr int n = N + 1;
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    double r = 0.0, lmax = 0.0;
-    if (i < a.ncells) {
+    double rm = 0.0, lm = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < a.ncells; i += (int64_t)gridDim.x * kBlock) {
+        double r = 0.0, lmax = 0.0;
         const double h = a.q[i];
         const double ih = rcp(h);
         double qx[n], qy[n];
@@ -45,18 +49,18 @@ __global__ __launch_bounds__(kBlock) void k_eig(StepArgs a)
 #pragma unroll
         for (int k = 0; k < n; ++k) bad |= !isfinite(qx[k]) || !isfinite(qy[k]);
         flag_bad_at(a, bad, a.slots[a.sa].step);
-        if (!(r >= 0.0)) r = 0.0;
-        if (!(lmax >= 0.0)) lmax = 0.0;
+        if (r >= 0.0) rm = fmax(rm, r);
+        if (lmax >= 0.0) lm = fmax(lm, lmax);
     }
-    publish_max(&a.slots[a.sa].rbits, r);
-    publish_max(&a.slots[a.sa].lbits, lmax);
+    publish_ratio(a.slots[a.sa], rm);
+    publish_max(&a.slots[a.sa].lbits, lm);
 }
 
 __global__ void k_slots_reset(Slot *slots, ErrWord *err, int sa)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         for (int s = 0; s < 3; ++s) {
-            slots[s].rbits = 0ull;
+            for (int w = 0; w < kRatioWords; ++w) slots[s].r[w].bits = 0ull;
             slots[s].lbits = 0ull;
             slots[s].t = 0.0;
             slots[s].dt = 0.0;
@@ -84,7 +88,7 @@ __global__ __launch_bounds__(kBlock) void k_permute(const double *src, int64_t s
 hipError_t launch_eig(int dim, int kind, int level, const StepArgs &a, hipStream_t s)
 {
     (void)dim;
-    const unsigned grid = blocks_for(a.ncells);
+    const unsigned grid = std::min(blocks_for(a.ncells), 1024u);
 #define LE1(N) hipLaunchKernelGGL((k_eig<N, 1>), dim3(grid), dim3(kBlock), 0, s, a)
 #define LE2(N) hipLaunchKernelGGL((k_eig<N, 2>), dim3(grid), dim3(kBlock), 0, s, a)
 #define LE3(N) hipLaunchKernelGGL((k_eig<N, 3>), dim3(grid), dim3(kBlock), 0, s, a)

@@ -93,7 +93,7 @@ __global__ __launch_bounds__(kBlock) void k_step_1d(StepArgs a)
             if (!(r >= 0.0)) r = 0.0;
         }
     }
-    publish_max(&a.slots[a.sb].rbits, r);
+    publish_ratio(a.slots[a.sb], r);
 }
 
 }  // namespace

@@ -30,7 +30,7 @@ __global__ __launch_bounds__(kBlock) void k_step_2d(StepArgs a)
     double rmax = 0.0;
     if (wave < nsx * nsy)  // waves beyond the grid only join the reduction
         rmax = band2d<N, CLOS>(a, dt, wave % nsx, wave / nsx);
-    publish_max(&a.slots[a.sb].rbits, rmax);
+    publish_ratio(a.slots[a.sb], rmax);
 }
 
 }  // namespace

@@ -174,7 +174,7 @@ __global__ __launch_bounds__(kBlock) void k_step_tri(StepArgs a)
         r = cfl_ratio_tri<N>(a.g, h, ih, qx, qy, fnx, fny, fw, &lm);
         if (!(r >= 0.0)) r = 0.0;
     }
-    publish_max(&a.slots[a.sb].rbits, r);
+    publish_ratio(a.slots[a.sb], r);
 }
 
 }  // namespace

@@ -11,17 +11,35 @@ namespace sme {
 
 // Per-step bookkeeping on the device.  Three slots rotate: step n reads slot a
 // (time, CFL ratio of Q^n), writes slot b (time and CFL ratio of Q^{n+1}) and
-// clears slot c for step n + 1.  rbits holds max_i r_i (r_i = sum_f |e_f| lam /
-// (2 |V_i|)) as the bit pattern of a non-negative double, so an unsigned
-// atomic max is an exact, order-independent maximum.
+// clears slot c for step n + 1.  The ratio words hold max_i r_i (r_i = sum_f
+// |e_f| lam / (2 |V_i|)) as the bit pattern of a non-negative double, so an
+// unsigned atomic max is an exact, order-independent maximum.
+// The max CFL ratio of a state is reduced into kRatioWords words, one per
+// compute die (block b publishes into word b % kRatioWords), each on its own
+// 256-byte line, so the per-block atomics of a step spread over eight
+// addresses instead of queueing on one; readers take the max of the words.
+constexpr int kRatioWords = 8;
+struct alignas(256) RatioWord {
+    unsigned long long bits;    // bit pattern of a non-negative double
+};
+
 struct Slot {
-    unsigned long long rbits;   // max CFL ratio of the state this slot describes
+    RatioWord r[kRatioWords];   // max CFL ratio of the state this slot describes
     unsigned long long lbits;   // max lam over cells and face normals
     double t;                   // simulated time of that state
     double dt;                  // step that produced it
     long long step;             // number of steps that advanced the state
-    long long pad[3];
 };
+
+// max CFL ratio held by a slot (host or device)
+__host__ __device__ inline double slot_ratio(const Slot &s)
+{
+    unsigned long long m = 0;
+    for (int w = 0; w < kRatioWords; ++w) m = s.r[w].bits > m ? s.r[w].bits : m;
+    double d;
+    __builtin_memcpy(&d, &m, sizeof d);
+    return d;
+}
 
 struct ErrWord {
     unsigned int flag;          // 1 once a non-physical value was produced

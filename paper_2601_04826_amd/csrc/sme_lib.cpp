@@ -611,14 +611,15 @@ int sme_eigmax(sme_ctx *c, double *lam_max, double *dt)
 {
     if (!c) return SME_EINVAL;
     if (!c->has_state) return fail(c, SME_EINVAL, "no state loaded");
-    HIPCHK(c, hipMemsetAsync(c->slots + c->sa, 0, 2 * sizeof(unsigned long long), c->stream));
+    // clear the ratio words and the speed of the current slot (they precede t)
+    HIPCHK(c, hipMemsetAsync(c->slots + c->sa, 0, offsetof(Slot, t), c->stream));
     StepArgs a = make_args(c);
     HIPCHK(c, launch_eig(0, c->kind, c->level, a, c->stream));
     Slot s;
     int r = read_slot(c, &s, nullptr);
     if (r) return r;
     double rr, ll;
-    memcpy(&rr, &s.rbits, sizeof rr);
+    rr = slot_ratio(s);
     memcpy(&ll, &s.lbits, sizeof ll);
     if (lam_max) *lam_max = ll;
     if (dt) *dt = rr > 0 ? c->p.cfl / rr : 0.0;

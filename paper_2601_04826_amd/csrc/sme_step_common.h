@@ -41,7 +41,7 @@ __device__ __forceinline__ double step_dt(const StepArgs &a)
     if (a.dt_fixed > 0.0) {
         dt = a.dt_fixed;
     } else {
-        double r = __longlong_as_double((long long)sl.rbits);
+        const double r = slot_ratio(sl);
         dt = r > 0.0 ? a.cfl / r : 0.0;
     }
     if (a.t_end > 0.0) dt = fmin(dt, fmax(a.t_end - sl.t, 0.0));
@@ -56,7 +56,8 @@ __device__ __forceinline__ void slot_update(const StepArgs &a, double dt)
     nx.t = sl.t + dt;
     nx.dt = dt;
     nx.step = sl.step + (dt > 0.0 ? 1 : 0);
-    a.slots[a.sc].rbits = 0ull;
+#pragma unroll
+    for (int w = 0; w < kRatioWords; ++w) a.slots[a.sc].r[w].bits = 0ull;
     a.slots[a.sc].lbits = 0ull;
 }
 
@@ -72,7 +73,8 @@ __device__ __forceinline__ void noop_step(const StepArgs &a, int nf)
     for (int f = 0; f < nf; ++f)
         for (int64_t i = t0; i < a.ncells; i += nth) a.qn[f * a.stride + i] = a.q[f * a.stride + i];
     if (t0 == 0) {
-        a.slots[a.sb].rbits = a.slots[a.sa].rbits;
+#pragma unroll
+        for (int w = 0; w < kRatioWords; ++w) a.slots[a.sb].r[w].bits = a.slots[a.sa].r[w].bits;
         a.slots[a.sb].lbits = a.slots[a.sa].lbits;
     }
 }
@@ -98,6 +100,12 @@ __device__ __forceinline__ void publish_max(unsigned long long *dst, double v)
         for (int w = 1; w < kBlock / kWave; ++w) m = fmax(m, part[w]);
         if (m > 0.0) atomicMax(dst, (unsigned long long)__double_as_longlong(m));
     }
+}
+
+// Block-wide maximum of a CFL ratio into the ratio word of this block's die.
+__device__ __forceinline__ void publish_ratio(Slot &s, double v)
+{
+    publish_max(&s.r[blockIdx.x % kRatioWords].bits, v);
 }
 
 // Block-wide sum of a per-lane count, one atomic add per block if nonzero.
