@@ -199,16 +199,31 @@ int sme_mlp_set_params(sme_mlp *m, const float *params, int on_device);
 int sme_mlp_get_params(sme_mlp *m, float *params, int on_device);
 /* Normalisation (mu, sigma: 9 each), output scale (2) and the training box of
  * the raw features (box_lo, box_hi: 9 each, FP64); outside the box a cell
- * counts as out of range (sme_closure_out_of_range). */
+ * counts as out of range (sme_closure_out_of_range).  Any pointer may be NULL
+ * (that part is kept).  Until set: mu 0, sigma 1, out_scale 1, no box. */
 int sme_mlp_set_scaling(sme_mlp *m, const float *mu, const float *sigma, const float *out_scale,
                         const double *box_lo, const double *box_hi);
-/* Device arrays, normalised: x [batch][9] -> y [batch][2]. */
+/* Scaling from n training samples (device arrays feat [n][9], targ [n][2],
+ * raw): mu = column means, sigma = sample standard deviations (at least
+ * 1e-6), out_scale = target standard deviations (at least 1e-12), box =
+ * [min - margin*span, max + margin*span] per feature; FP64 two-pass sums in a
+ * fixed order, so the result is deterministic.  Synchronises. */
+int sme_mlp_fit_scaling(sme_mlp *m, const float *feat, const float *targ, int64_t n, double margin);
+/* The current scaling (host arrays; any pointer may be NULL). */
+int sme_mlp_get_scaling(const sme_mlp *m, float *mu, float *sigma, float *out_scale, double *box_lo,
+                        double *box_hi);
+/* Device arrays, raw features x [batch][9] -> normalised outputs y~ [batch][2];
+ * the network normalises its inputs with its scaling. */
 int sme_mlp_forward(sme_mlp *m, const float *x, int64_t batch, float *y);
-/* MSE loss L = (1/batch) sum |y~ - t~|^2 and its gradient (device, 4930;
- * NULL skips the copy); loss into host memory (NULL: no synchronisation). */
-int sme_mlp_loss_grad(sme_mlp *m, const float *x, const float *t, int64_t batch, float *loss, float *grad);
-/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on a batch. */
-int sme_mlp_train_step(sme_mlp *m, const float *x, const float *t, int64_t batch, float lr, float *loss);
+/* MSE loss L = (1/batch) sum |y~ - t~|^2 (t~ = t / out_scale) and its
+ * gradient (device, 4930; NULL skips the copy); loss into host memory (NULL:
+ * no synchronisation).  x [.][9] and t [.][2] hold raw samples; the batch is
+ * rows idx[0..batch-1] (device int64; NULL: rows 0..batch-1). */
+int sme_mlp_loss_grad(sme_mlp *m, const float *x, const float *t, const int64_t *idx, int64_t batch, float *loss,
+                      float *grad);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on a batch (as above). */
+int sme_mlp_train_step(sme_mlp *m, const float *x, const float *t, const int64_t *idx, int64_t batch, float lr,
+                       float *loss);
 int sme_mlp_reset_optimizer(sme_mlp *m);
 const char *sme_mlp_last_error(const sme_mlp *m);
 void sme_mlp_destroy(sme_mlp *m);

@@ -2,9 +2,11 @@
 
 Everything numeric runs in the library's kernels: the level-8 and level-1 SME
 steps that generate the data, the sample extraction (features and a-priori
-targets), the FP32 training step (forward, backward, Adam) and the inference
-fused into the level-1 step.  This module only orchestrates them; torch holds
-device buffers and does the batch shuffling.
+targets), the feature statistics behind the scaling and the training box, the
+FP32 training step (forward, backward, Adam, batches gathered by index) and
+the rates pass before every level-1 step.  This module only orchestrates
+them: torch holds device buffers, a seeded numpy generator draws the sampled
+cells and the batch permutations.
 
 Target (a-priori closure): for consecutive level-8 states Q8^n, Q8^{n+1} with
 step dt, r = [P(Q8^{n+1}) - Step_L1(P(Q8^n))] / dt on (q_0, q_1), where P keeps
@@ -35,9 +37,12 @@ def generate(seeds, n=4096, steps=2000, every=10, cells_per_snapshot=256, stream
 
     Returns (features [S, 9], targets [S, 2]) as float32 CUDA tensors."""
     st = stream or torch.cuda.Stream()
-    gen = torch.Generator(device="cuda")
-    gen.manual_seed(rng_seed)
-    feats, targs = [], []
+    rng = np.random.default_rng(rng_seed)
+    snaps = len(range(0, steps, every))
+    total = len(seeds) * snaps * cells_per_snapshot
+    feat = torch.empty((total, N_IN), dtype=torch.float32, device="cuda")
+    targ = torch.empty((total, N_OUT), dtype=torch.float32, device="cuda")
+    at = 0
     with torch.cuda.stream(st):
         for seed in seeds:
             p8 = workloads.smooth_1d(n=n, level=8, seed=seed, steps=steps)
@@ -58,14 +63,15 @@ def generate(seeds, n=4096, steps=2000, every=10, cells_per_snapshot=256, stream
                 s1.set_state(q8[:3])
                 s1.step(dt)
                 s1.get_state(q1)
-                cells = torch.randperm(n, device="cuda", generator=gen)[:cells_per_snapshot]
-                f, t = sme.closure_samples(q8, q8n, q1, dt, cells, stream=st.cuda_stream)
-                feats.append(f)
-                targs.append(t)
+                cells = torch.from_numpy(rng.choice(n, size=cells_per_snapshot, replace=False).astype(np.int64)).cuda()
+                sme.closure_samples(q8, q8n, q1, dt, cells, stream=st.cuda_stream,
+                                    out=(feat[at:at + cells_per_snapshot], targ[at:at + cells_per_snapshot]))
+                at += cells_per_snapshot
             s8.close()
             s1.close()
         st.synchronize()
-    return torch.cat(feats), torch.cat(targs)
+    assert at == total
+    return feat, targ
 
 
 def init_params(seed=0):
@@ -78,62 +84,33 @@ def init_params(seed=0):
     return np.concatenate(parts).astype(np.float32)
 
 
-class Scaling:
-    """Input normalisation, output scale and the training box of the raw features."""
-
-    def __init__(self, feat, targ, margin=0.1):
-        f = feat.double()
-        self.mu = feat.mean(0).float()
-        self.sigma = torch.clamp(feat.std(0), min=1e-6).float()
-        self.out_scale = torch.clamp(targ.std(0), min=1e-12).float()
-        lo, hi = f.min(0).values, f.max(0).values
-        span = hi - lo
-        self.box_lo = (lo - margin * span).cpu().numpy()
-        self.box_hi = (hi + margin * span).cpu().numpy()
-
-    def inputs(self, feat):
-        # same FP32 arithmetic as the kernels: (f - mu) * (1 / sigma)
-        return ((feat - self.mu) * (1.0 / self.sigma)).contiguous()
-
-    def targets(self, targ):
-        return (targ / self.out_scale).contiguous()
-
-    def apply(self, mlp):
-        mlp.set_scaling(self.mu.cpu().numpy(), self.sigma.cpu().numpy(), self.out_scale.cpu().numpy(),
-                        self.box_lo, self.box_hi)
-
-
-def fit(feat, targ, epochs=20, batch=4096, lr=2e-3, lr_end=1e-4, seed=0, stream=None, log=None):
+def fit(feat, targ, epochs=20, batch=4096, lr=2e-3, lr_end=1e-4, seed=0, stream=None, log=None, margin=0.1):
     """Train the network with the library's FP32 kernels (Adam, MSE on
-    normalised targets); returns (MLP, Scaling, loss history)."""
+    normalised targets) on raw samples; the scaling and the training box come
+    from the library's statistics of the same samples.  Returns (MLP, scaling
+    dict, loss history)."""
     st = stream or torch.cuda.Stream()
-    sc = Scaling(feat, targ)
+    rng = np.random.default_rng(seed)
     with torch.cuda.stream(st):
-        x = sc.inputs(feat)
-        t = sc.targets(targ)
         mlp = sme.MLP(init_params(seed), stream=st.cuda_stream)
-        gen = torch.Generator(device="cuda")
-        gen.manual_seed(seed)
-        S = x.shape[0]
+        sc = mlp.fit_scaling(feat, targ, margin=margin)
+        S = feat.shape[0]
         nb = max(1, S // batch)
         total = epochs * nb
         hist = []
         step = 0
         for ep in range(epochs):
-            perm = torch.randperm(S, device="cuda", generator=gen)
+            perm = torch.from_numpy(rng.permutation(S).astype(np.int64)).cuda()
             for b in range(nb):
                 idx = perm[b * batch:(b + 1) * batch]
-                xb = x.index_select(0, idx).contiguous()
-                tb = t.index_select(0, idx).contiguous()
                 frac = step / max(1, total - 1)
                 rate = lr * (lr_end / lr) ** frac  # geometric decay
                 want = b == nb - 1
-                loss = mlp.train_step(xb, tb, rate, want_loss=want)
+                loss = mlp.train_step(feat, targ, rate, idx=idx, want_loss=want)
                 step += 1
             hist.append(loss)
             if log:
                 log(f"epoch {ep + 1}/{epochs} loss {loss:.5f}")
-        sc.apply(mlp)
         st.synchronize()
     return mlp, sc, hist
 

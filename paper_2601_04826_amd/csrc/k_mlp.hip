@@ -1,6 +1,11 @@
 // k_mlp.hip -- FP32 training kernels of the closure network, and the kernel
 // that turns level-8 snapshots into training samples.
 //
+// Every kernel reads raw features and targets and normalises them with the
+// network's scaling, x~ = (x - mu) * (1/sigma) and t~ = t / s_out (the same
+// FP32 arithmetic as inference); training kernels take their batch rows
+// through an index list (NULL: rows 0..B-1).
+//
 // Training step for a batch of B samples (normalised inputs x~, targets t~):
 //   k_mlp_grad     one 64-lane wave per 64 samples: forward, reverse-mode
 //                  backward, and that block's partial sums of every parameter
@@ -10,6 +15,11 @@
 //   k_mlp_reduce   sums the block partials per parameter in a fixed order
 //                  (deterministic), FP64 accumulation
 //   k_mlp_adam     Adam update with bias correction (Kingma & Ba)
+// Feature statistics (for the scaling and the training box):
+//   k_mlp_stats    per block, FP64 column sums (or sums of squared deviations
+//                  from a given mean) of 9 features and 2 targets, and the
+//                  feature minima and maxima
+//   k_mlp_stats_reduce  fixed-order sum over the blocks (deterministic)
 #include <hip/hip_runtime.h>
 
 #include "sme_kernels.h"
@@ -23,7 +33,7 @@ constexpr int kGradBlock = 64;  // samples (= lanes) per gradient block
 constexpr int kLdsPad = kMlpHid + 1;
 
 __global__ __launch_bounds__(256) void k_mlp_forward(const float *__restrict__ params, const float *__restrict__ x,
-                                                     int64_t B, float *__restrict__ y)
+                                                     int64_t B, MlpScale sc, float *__restrict__ y)
 {
     __shared__ float P[kMlpParams];
     mlp_stage(params, P);
@@ -31,14 +41,15 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const float *__restrict__ p
     if (b >= B) return;
     float xi[kMlpIn], a1[kMlpHid], a2[kMlpHid], yo[kMlpOut];
 #pragma unroll
-    for (int i = 0; i < kMlpIn; ++i) xi[i] = x[b * kMlpIn + i];
+    for (int i = 0; i < kMlpIn; ++i) xi[i] = (x[b * kMlpIn + i] - sc.mu[i]) * sc.inv_sigma[i];
     mlp_forward(P, xi, a1, a2, yo);
 #pragma unroll
     for (int o = 0; o < kMlpOut; ++o) y[b * kMlpOut + o] = yo[o];
 }
 
 __global__ __launch_bounds__(kGradBlock) void k_mlp_grad(const float *__restrict__ params, const float *__restrict__ x,
-                                                         const float *__restrict__ t, int64_t B, float inv_b,
+                                                         const float *__restrict__ t, const int64_t *__restrict__ idx,
+                                                         int64_t B, float inv_b, MlpScale sc,
                                                          float *__restrict__ partial, float *__restrict__ partial_loss)
 {
     __shared__ float P[kMlpParams];
@@ -52,16 +63,17 @@ __global__ __launch_bounds__(kGradBlock) void k_mlp_grad(const float *__restrict
     const int tid = threadIdx.x;
     const int64_t b = (int64_t)blockIdx.x * kGradBlock + tid;
     const bool live = b < B;
+    const int64_t row = live ? (idx ? idx[b] : b) : 0;
     float xi[kMlpIn], a1[kMlpHid], a2[kMlpHid], y[kMlpOut];
 #pragma unroll
-    for (int i = 0; i < kMlpIn; ++i) xi[i] = live ? x[b * kMlpIn + i] : 0.0f;
+    for (int i = 0; i < kMlpIn; ++i) xi[i] = live ? (x[row * kMlpIn + i] - sc.mu[i]) * sc.inv_sigma[i] : 0.0f;
     mlp_forward(P, xi, a1, a2, y);
     // backward of one sample; samples beyond B contribute nothing
     float dy[kMlpOut];
     float loss = 0.0f;
 #pragma unroll
     for (int o = 0; o < kMlpOut; ++o) {
-        const float r = live ? y[o] - t[b * kMlpOut + o] : 0.0f;
+        const float r = live ? y[o] - t[row * kMlpOut + o] / sc.out_scale[o] : 0.0f;
         loss = fmaf(r, r, loss);
         dy[o] = 2.0f * r * inv_b;
     }
@@ -164,6 +176,75 @@ __global__ __launch_bounds__(256) void k_mlp_adam(float *__restrict__ p, const f
     p[k] -= lr * (mk * c1) / (sqrtf(vk * c2) + eps);
 }
 
+constexpr int kStatCols = kMlpIn + kMlpOut;  // 9 features, 2 targets
+constexpr int kStatBlocks = 256;
+constexpr int kStatWidth = kStatCols + 2 * kMlpIn;  // sums, feature minima, feature maxima
+
+// value of column c of row r (features first, then targets)
+__device__ __forceinline__ double stat_col(const float *feat, const float *targ, int64_t r, int c)
+{
+    return c < kMlpIn ? (double)feat[r * kMlpIn + c] : (double)targ[r * kMlpOut + c - kMlpIn];
+}
+
+// mean == nullptr: column sums, minima and maxima; else sums of squared
+// deviations from mean.  One row per thread and stride; tree sums in LDS.
+__global__ __launch_bounds__(256) void k_mlp_stats(const float *__restrict__ feat, const float *__restrict__ targ,
+                                                   int64_t n, const double *__restrict__ mean,
+                                                   double *__restrict__ partial)
+{
+    __shared__ double S[256][kStatWidth + 1];
+    double acc[kStatWidth];
+#pragma unroll
+    for (int c = 0; c < kStatCols; ++c) acc[c] = 0.0;
+#pragma unroll
+    for (int c = 0; c < kMlpIn; ++c) {
+        acc[kStatCols + c] = INFINITY;
+        acc[kStatCols + kMlpIn + c] = -INFINITY;
+    }
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
+#pragma unroll
+        for (int c = 0; c < kStatCols; ++c) {
+            const double v = stat_col(feat, targ, r, c);
+            if (mean) {
+                const double d = v - mean[c];
+                acc[c] = fma(d, d, acc[c]);
+            } else {
+                acc[c] += v;
+                if (c < kMlpIn) {
+                    acc[kStatCols + c] = fmin(acc[kStatCols + c], v);
+                    acc[kStatCols + kMlpIn + c] = fmax(acc[kStatCols + kMlpIn + c], v);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < kStatWidth; ++c) S[threadIdx.x][c] = acc[c];
+    __syncthreads();
+    for (int half = 128; half > 0; half >>= 1) {
+        if ((int)threadIdx.x < half) {
+            for (int c = 0; c < kStatWidth; ++c) {
+                const double o = S[threadIdx.x + half][c];
+                double &v = S[threadIdx.x][c];
+                v = c < kStatCols ? v + o : (c < kStatCols + kMlpIn ? fmin(v, o) : fmax(v, o));
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < kStatWidth) partial[(int64_t)blockIdx.x * kStatWidth + threadIdx.x] = S[0][threadIdx.x];
+}
+
+__global__ void k_mlp_stats_reduce(const double *__restrict__ partial, int nblk, double *__restrict__ out)
+{
+    const int c = threadIdx.x;
+    if (c >= kStatWidth) return;
+    double v = partial[c];
+    for (int b = 1; b < nblk; ++b) {
+        const double o = partial[(int64_t)b * kStatWidth + c];
+        v = c < kStatCols ? v + o : (c < kStatCols + kMlpIn ? fmin(v, o) : fmax(v, o));
+    }
+    out[c] = v;
+}
+
 // Training samples from two consecutive level-8 states and the level-1 step of
 // the first (all on a periodic 1D row, SoA with the given strides).  Sample s
 // is cell cells[s]: raw features (FP64 differences, stored FP32) and target
@@ -198,22 +279,39 @@ __global__ __launch_bounds__(256) void k_closure_samples(const double *__restric
 
 }  // namespace
 
-hipError_t launch_mlp_forward(const float *params, const float *x, int64_t B, float *y, hipStream_t s)
+hipError_t launch_mlp_forward(const float *params, const float *x, int64_t B, const MlpScale &sc, float *y,
+                              hipStream_t s)
 {
     if (B <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_mlp_forward, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, s, params, x, B, y);
+    hipLaunchKernelGGL(k_mlp_forward, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, s, params, x, B, sc, y);
+    return hipGetLastError();
+}
+
+int mlp_stat_width() { return kStatWidth; }
+int mlp_stat_blocks() { return kStatBlocks; }
+
+hipError_t launch_mlp_stats(const float *feat, const float *targ, int64_t n, const double *mean, double *partial,
+                            double *out, hipStream_t s)
+{
+    if (n <= 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_mlp_stats, dim3(kStatBlocks), dim3(256), 0, s, feat, targ, n, mean, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_mlp_stats_reduce, dim3(1), dim3(64), 0, s, partial, kStatBlocks, out);
     return hipGetLastError();
 }
 
 int mlp_grad_blocks(int64_t B) { return (int)((B + kGradBlock - 1) / kGradBlock); }
 
-hipError_t launch_mlp_grad(const float *params, const float *x, const float *t, int64_t B, float *partial,
-                           float *partial_loss, float *grad, float *loss, hipStream_t s)
+hipError_t launch_mlp_grad(const float *params, const float *x, const float *t, const int64_t *idx, int64_t B,
+                           const MlpScale &sc, float *partial, float *partial_loss, float *grad, float *loss,
+                           hipStream_t s)
 {
     if (B <= 0) return hipErrorInvalidValue;
     const int nblk = mlp_grad_blocks(B);
     const float inv_b = 1.0f / (float)B;
-    hipLaunchKernelGGL(k_mlp_grad, dim3(nblk), dim3(kGradBlock), 0, s, params, x, t, B, inv_b, partial, partial_loss);
+    hipLaunchKernelGGL(k_mlp_grad, dim3(nblk), dim3(kGradBlock), 0, s, params, x, t, idx, B, inv_b, sc, partial,
+                       partial_loss);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_mlp_reduce, dim3((kMlpParams + 255) / 256), dim3(256), 0, s, partial, partial_loss, nblk,

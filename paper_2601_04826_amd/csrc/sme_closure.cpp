@@ -1,12 +1,14 @@
 // sme_closure.cpp -- host side of the learned closure (sme_mlp_*, sme_closure_*).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "../../include/sme.h"
 #include "sme_kernels.h"
@@ -28,6 +30,7 @@ struct sme_mlp {
     float *m = nullptr, *v = nullptr, *g = nullptr, *loss = nullptr;
     float *partial = nullptr, *partial_loss = nullptr;
     int partial_blocks = 0;
+    double *stat_partial = nullptr, *stat_out = nullptr, *stat_mean = nullptr;  // feature statistics
     int64_t t = 0;             // Adam step count
     std::string last;
 };
@@ -94,6 +97,17 @@ bool fold_fp16(ClosureModel &cm)
         H.c3[o] = P[kOffB3 + o];
     }
     return wmax <= 65504.0;
+}
+
+MlpScale scale_of(const sme_mlp *m)
+{
+    MlpScale sc{};
+    for (int i = 0; i < kMlpIn; ++i) {
+        sc.mu[i] = m->host.mu[i];
+        sc.inv_sigma[i] = m->host.inv_sigma[i];
+    }
+    for (int o = 0; o < kMlpOut; ++o) sc.out_scale[o] = m->host.out_scale[o];
+    return sc;
 }
 
 }  // namespace
@@ -171,19 +185,72 @@ int sme_mlp_set_scaling(sme_mlp *m, const float *mu, const float *sigma, const f
     return SME_OK;
 }
 
-int sme_mlp_forward(sme_mlp *m, const float *x, int64_t batch, float *y)
+int sme_mlp_get_scaling(const sme_mlp *m, float *mu, float *sigma, float *out_scale, double *box_lo,
+                        double *box_hi)
 {
-    if (!m || !x || !y || batch < 0) return SME_EINVAL;
-    MCHK(m, launch_mlp_forward(m->p, x, batch, y, m->stream));
+    if (!m) return SME_EINVAL;
+    for (int i = 0; i < kMlpIn; ++i) {
+        if (mu) mu[i] = m->host.mu[i];
+        if (sigma) sigma[i] = 1.0f / m->host.inv_sigma[i];
+        if (box_lo) box_lo[i] = m->host.box_lo[i];
+        if (box_hi) box_hi[i] = m->host.box_hi[i];
+    }
+    if (out_scale)
+        for (int o = 0; o < kMlpOut; ++o) out_scale[o] = m->host.out_scale[o];
     return SME_OK;
 }
 
-int sme_mlp_loss_grad(sme_mlp *m, const float *x, const float *t, int64_t batch, float *loss, float *grad)
+int sme_mlp_fit_scaling(sme_mlp *m, const float *feat, const float *targ, int64_t n, double margin)
+{
+    if (!m || !feat || !targ || n < 2 || !(margin >= 0.0)) return SME_EINVAL;
+    const int w = mlp_stat_width();
+    if (!m->stat_partial) {
+        MCHK(m, hipMalloc((void **)&m->stat_partial, (size_t)mlp_stat_blocks() * w * sizeof(double)));
+        MCHK(m, hipMalloc((void **)&m->stat_out, w * sizeof(double)));
+        MCHK(m, hipMalloc((void **)&m->stat_mean, w * sizeof(double)));
+    }
+    std::vector<double> first(w), second(w), mean(w, 0.0);
+    // pass 1: sums, minima, maxima; pass 2: squared deviations from the mean
+    MCHK(m, launch_mlp_stats(feat, targ, n, nullptr, m->stat_partial, m->stat_out, m->stream));
+    MCHK(m, hipMemcpyAsync(first.data(), m->stat_out, w * sizeof(double), hipMemcpyDeviceToHost, m->stream));
+    MCHK(m, hipStreamSynchronize(m->stream));
+    constexpr int cols = kMlpIn + kMlpOut;
+    for (int c = 0; c < cols; ++c) mean[c] = first[c] / (double)n;
+    MCHK(m, hipMemcpyAsync(m->stat_mean, mean.data(), w * sizeof(double), hipMemcpyHostToDevice, m->stream));
+    MCHK(m, launch_mlp_stats(feat, targ, n, m->stat_mean, m->stat_partial, m->stat_out, m->stream));
+    MCHK(m, hipMemcpyAsync(second.data(), m->stat_out, w * sizeof(double), hipMemcpyDeviceToHost, m->stream));
+    MCHK(m, hipStreamSynchronize(m->stream));
+    for (int c = 0; c < cols; ++c) {
+        const double sd = std::sqrt(second[c] / (double)(n - 1));  // sample standard deviation
+        if (c < kMlpIn) {
+            const float sigma = std::max((float)sd, 1e-6f);
+            const double lo = first[cols + c], hi = first[cols + kMlpIn + c], span = hi - lo;
+            m->host.mu[c] = (float)mean[c];
+            m->host.inv_sigma[c] = 1.0f / sigma;
+            m->host.box_lo[c] = lo - margin * span;
+            m->host.box_hi[c] = hi + margin * span;
+        } else {
+            m->host.out_scale[c - kMlpIn] = std::max((float)sd, 1e-12f);
+        }
+    }
+    return SME_OK;
+}
+
+int sme_mlp_forward(sme_mlp *m, const float *x, int64_t batch, float *y)
+{
+    if (!m || !x || !y || batch < 0) return SME_EINVAL;
+    MCHK(m, launch_mlp_forward(m->p, x, batch, scale_of(m), y, m->stream));
+    return SME_OK;
+}
+
+int sme_mlp_loss_grad(sme_mlp *m, const float *x, const float *t, const int64_t *idx, int64_t batch, float *loss,
+                      float *grad)
 {
     if (!m || !x || !t || batch < 1) return SME_EINVAL;
     int r = ensure_partials(m, batch);
     if (r) return r;
-    MCHK(m, launch_mlp_grad(m->p, x, t, batch, m->partial, m->partial_loss, m->g, m->loss, m->stream));
+    MCHK(m, launch_mlp_grad(m->p, x, t, idx, batch, scale_of(m), m->partial, m->partial_loss, m->g, m->loss,
+                            m->stream));
     if (grad) MCHK(m, hipMemcpyAsync(grad, m->g, kMlpParams * sizeof(float), hipMemcpyDeviceToDevice, m->stream));
     if (loss) {
         MCHK(m, hipMemcpyAsync(loss, m->loss, sizeof(float), hipMemcpyDeviceToHost, m->stream));
@@ -192,12 +259,14 @@ int sme_mlp_loss_grad(sme_mlp *m, const float *x, const float *t, int64_t batch,
     return SME_OK;
 }
 
-int sme_mlp_train_step(sme_mlp *m, const float *x, const float *t, int64_t batch, float lr, float *loss)
+int sme_mlp_train_step(sme_mlp *m, const float *x, const float *t, const int64_t *idx, int64_t batch, float lr,
+                       float *loss)
 {
     if (!m || !x || !t || batch < 1 || !(lr > 0)) return SME_EINVAL;
     int r = ensure_partials(m, batch);
     if (r) return r;
-    MCHK(m, launch_mlp_grad(m->p, x, t, batch, m->partial, m->partial_loss, m->g, m->loss, m->stream));
+    MCHK(m, launch_mlp_grad(m->p, x, t, idx, batch, scale_of(m), m->partial, m->partial_loss, m->g, m->loss,
+                            m->stream));
     m->t += 1;
     const double b1 = 0.9, b2 = 0.999;
     const float c1 = (float)(1.0 / (1.0 - std::pow(b1, (double)m->t)));
@@ -232,6 +301,9 @@ void sme_mlp_destroy(sme_mlp *m)
     (void)hipFree(m->loss);
     (void)hipFree(m->partial);
     (void)hipFree(m->partial_loss);
+    (void)hipFree(m->stat_partial);
+    (void)hipFree(m->stat_out);
+    (void)hipFree(m->stat_mean);
     if (m->own_stream) (void)hipStreamDestroy(m->stream);
     delete m;
 }

@@ -121,10 +121,17 @@ hipError_t launch_step_tri(int level, const StepArgs &a, hipStream_t s);
 hipError_t launch_eig(int dim, int kind, int level, const StepArgs &a, hipStream_t s);
 hipError_t launch_slots_reset(Slot *slots, ErrWord *err, int sa, hipStream_t s);  // err may be null
 // closure network training and samples (k_mlp.hip)
-hipError_t launch_mlp_forward(const float *params, const float *x, int64_t B, float *y, hipStream_t s);
+hipError_t launch_mlp_forward(const float *params, const float *x, int64_t B, const MlpScale &sc, float *y,
+                              hipStream_t s);
 int mlp_grad_blocks(int64_t B);
-hipError_t launch_mlp_grad(const float *params, const float *x, const float *t, int64_t B, float *partial,
-                           float *partial_loss, float *grad, float *loss, hipStream_t s);
+hipError_t launch_mlp_grad(const float *params, const float *x, const float *t, const int64_t *idx, int64_t B,
+                           const MlpScale &sc, float *partial, float *partial_loss, float *grad, float *loss,
+                           hipStream_t s);
+// feature statistics: out = [sums or squared-deviation sums of 11 columns, 9 minima, 9 maxima]
+int mlp_stat_width();
+int mlp_stat_blocks();
+hipError_t launch_mlp_stats(const float *feat, const float *targ, int64_t n, const double *mean, double *partial,
+                            double *out, hipStream_t s);
 hipError_t launch_mlp_adam(float *p, const float *g, float *m, float *v, float lr, float b1, float b2, float eps,
                            float c1, float c2, hipStream_t s);
 hipError_t launch_closure_samples(const double *q8, int64_t s8, const double *q8n, int64_t s8n, const double *q1,

@@ -51,6 +51,14 @@ constexpr int kFoldPerm(int p)
 
 enum ClosurePrecision { kClosureFp32 = 0, kClosureFp16Mfma = 1 };
 
+// Normalisation of the network's inputs and targets, passed to the training
+// and forward kernels by value.
+struct MlpScale {
+    float mu[kMlpIn];
+    float inv_sigma[kMlpIn];
+    float out_scale[kMlpOut];
+};
+
 // Everything the closure rates pass needs.
 struct ClosureModel {
     float params[kMlpParams];

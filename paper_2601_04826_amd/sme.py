@@ -33,7 +33,8 @@ EXPORTS = [
     "sme_batch_init", "sme_batch_set_state", "sme_batch_get_state", "sme_batch_run", "sme_batch_time",
     "sme_batch_cells", "sme_batch_rows", "sme_batch_set_rows", "sme_batch_autotune",
     "sme_batch_last_error", "sme_batch_destroy",
-    "sme_mlp_create", "sme_mlp_set_params", "sme_mlp_get_params", "sme_mlp_set_scaling", "sme_mlp_forward",
+    "sme_mlp_create", "sme_mlp_set_params", "sme_mlp_get_params", "sme_mlp_set_scaling", "sme_mlp_fit_scaling",
+    "sme_mlp_get_scaling", "sme_mlp_forward",
     "sme_mlp_loss_grad", "sme_mlp_train_step", "sme_mlp_reset_optimizer", "sme_mlp_last_error", "sme_mlp_destroy",
     "sme_closure_samples", "sme_closure_attach", "sme_closure_attach_ex", "sme_closure_out_of_range",
 ]
@@ -98,8 +99,10 @@ def _load():
         "sme_mlp_get_params": (i, [vp, vp, i]),
         "sme_mlp_set_scaling": (i, [vp, vp, vp, vp, vp, vp]),
         "sme_mlp_forward": (i, [vp, vp, i64, vp]),
-        "sme_mlp_loss_grad": (i, [vp, vp, vp, i64, vp, vp]),
-        "sme_mlp_train_step": (i, [vp, vp, vp, i64, ctypes.c_float, vp]),
+        "sme_mlp_fit_scaling": (i, [vp, vp, vp, i64, d]),
+        "sme_mlp_get_scaling": (i, [vp, vp, vp, vp, vp, vp]),
+        "sme_mlp_loss_grad": (i, [vp, vp, vp, vp, i64, vp, vp]),
+        "sme_mlp_train_step": (i, [vp, vp, vp, vp, i64, ctypes.c_float, vp]),
         "sme_mlp_reset_optimizer": (i, [vp]),
         "sme_mlp_last_error": (ctypes.c_char_p, [vp]),
         "sme_mlp_destroy": (None, [vp]),
@@ -431,25 +434,49 @@ class MLP:
         b = [np.ascontiguousarray(v, dtype=np.float64) for v in (box_lo, box_hi)]
         _mcheck(_lib.sme_mlp_set_scaling(self.ctx, *(x.ctypes.data_as(ctypes.c_void_p) for x in a + b)), self.ctx)
 
+    def fit_scaling(self, feat, targ, margin=0.1):
+        """Scaling and training box from raw samples (CUDA float32 [n, 9], [n, 2])."""
+        _mcheck(_lib.sme_mlp_fit_scaling(self.ctx, ctypes.c_void_p(feat.data_ptr()), ctypes.c_void_p(targ.data_ptr()),
+                                         feat.shape[0], float(margin)), self.ctx)
+        return self.get_scaling()
+
+    def get_scaling(self):
+        """dict of mu, sigma, out_scale (float32) and box_lo, box_hi (float64)."""
+        out = dict(mu=np.empty(9, np.float32), sigma=np.empty(9, np.float32), out_scale=np.empty(2, np.float32),
+                   box_lo=np.empty(9), box_hi=np.empty(9))
+        _mcheck(_lib.sme_mlp_get_scaling(self.ctx, *(out[k].ctypes.data_as(ctypes.c_void_p)
+                                                     for k in ("mu", "sigma", "out_scale", "box_lo", "box_hi"))),
+                self.ctx)
+        return out
+
     def forward(self, x):
-        """x: torch CUDA float32 [B, 9] (normalised) -> [B, 2]."""
+        """x: torch CUDA float32 [B, 9] raw features -> normalised outputs [B, 2]."""
         y = torch.empty((x.shape[0], 2), dtype=torch.float32, device=x.device)
         _mcheck(_lib.sme_mlp_forward(self.ctx, ctypes.c_void_p(x.data_ptr()), x.shape[0],
                                      ctypes.c_void_p(y.data_ptr())), self.ctx)
         return y
 
-    def loss_grad(self, x, t):
+    @staticmethod
+    def _rows(x, idx):
+        if idx is None:
+            return None, x.shape[0]
+        assert idx.dtype == torch.int64 and idx.is_cuda and idx.is_contiguous()
+        return ctypes.c_void_p(idx.data_ptr()), idx.shape[0]
+
+    def loss_grad(self, x, t, idx=None):
+        """Loss and gradient on rows idx (CUDA int64; None: all rows) of raw samples x, t."""
         g = torch.empty(NPARAM, dtype=torch.float32, device=x.device)
         loss = ctypes.c_float()
-        _mcheck(_lib.sme_mlp_loss_grad(self.ctx, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(t.data_ptr()),
-                                       x.shape[0], ctypes.byref(loss), ctypes.c_void_p(g.data_ptr())), self.ctx)
+        ip, nb = self._rows(x, idx)
+        _mcheck(_lib.sme_mlp_loss_grad(self.ctx, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(t.data_ptr()), ip,
+                                       nb, ctypes.byref(loss), ctypes.c_void_p(g.data_ptr())), self.ctx)
         return loss.value, g
 
-    def train_step(self, x, t, lr, want_loss=False):
+    def train_step(self, x, t, lr, idx=None, want_loss=False):
         loss = ctypes.c_float()
-        _mcheck(_lib.sme_mlp_train_step(self.ctx, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(t.data_ptr()),
-                                        x.shape[0], ctypes.c_float(lr),
-                                        ctypes.byref(loss) if want_loss else None), self.ctx)
+        ip, nb = self._rows(x, idx)
+        _mcheck(_lib.sme_mlp_train_step(self.ctx, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(t.data_ptr()), ip,
+                                        nb, ctypes.c_float(lr), ctypes.byref(loss) if want_loss else None), self.ctx)
         return loss.value if want_loss else None
 
     def reset_optimizer(self):
@@ -467,13 +494,18 @@ class MLP:
             pass
 
 
-def closure_samples(q8, q8_next, q1_step, dt, cells, stream=None):
+def closure_samples(q8, q8_next, q1_step, dt, cells, stream=None, out=None):
     """Training samples (features [S, 9], targets [S, 2], FP32 torch CUDA) from
-    torch CUDA float64 states [nf, n] of a periodic 1D row."""
+    torch CUDA float64 states [nf, n] of a periodic 1D row; out = (feat, targ)
+    writes them into given contiguous tensors."""
     n = q8.shape[1]
     ns = cells.shape[0]
-    feat = torch.empty((ns, 9), dtype=torch.float32, device=q8.device)
-    targ = torch.empty((ns, 2), dtype=torch.float32, device=q8.device)
+    if out is None:
+        feat = torch.empty((ns, 9), dtype=torch.float32, device=q8.device)
+        targ = torch.empty((ns, 2), dtype=torch.float32, device=q8.device)
+    else:
+        feat, targ = out
+        assert feat.shape == (ns, 9) and targ.shape == (ns, 2) and feat.is_contiguous() and targ.is_contiguous()
     if stream is None:
         stream = torch.cuda.current_stream().cuda_stream
     code = _lib.sme_closure_samples(ctypes.c_void_p(q8.data_ptr()), q8.stride(0), ctypes.c_void_p(q8_next.data_ptr()),

@@ -79,6 +79,57 @@ def test_adam_step_matches_oracle(env):
     m.close()
 
 
+def test_fit_scaling_matches_numpy(env):
+    torch, sme, _ = env
+    rng = np.random.default_rng(11)
+    n = 100003  # not a multiple of any block size
+    f = (rng.standard_normal((n, 9)) * rng.uniform(0.01, 3.0, 9) + rng.uniform(-2, 2, 9)).astype(np.float32)
+    t = (rng.standard_normal((n, 2)) * [1e-3, 0.3]).astype(np.float32)
+    m = sme.MLP(np.zeros(omlp.NPARAM, dtype=np.float32))
+    sc = m.fit_scaling(torch.from_numpy(f).cuda(), torch.from_numpy(t).cuda(), margin=0.1)
+    f64, t64 = f.astype(np.float64), t.astype(np.float64)
+    np.testing.assert_allclose(sc["mu"], f64.mean(0).astype(np.float32), rtol=1e-6, atol=1e-7)
+    np.testing.assert_allclose(sc["sigma"], f64.std(0, ddof=1).astype(np.float32), rtol=1e-6)
+    np.testing.assert_allclose(sc["out_scale"], t64.std(0, ddof=1).astype(np.float32), rtol=1e-6)
+    lo, hi = f64.min(0), f64.max(0)
+    np.testing.assert_allclose(sc["box_lo"], lo - 0.1 * (hi - lo), rtol=1e-15)
+    np.testing.assert_allclose(sc["box_hi"], hi + 0.1 * (hi - lo), rtol=1e-15)
+    m.close()
+
+
+def test_gradient_with_scaling_and_rows(env):
+    """Raw samples, a non-trivial scaling and a batch picked by index: the
+    kernels normalise in place exactly as the oracle's inputs are prepared."""
+    torch, sme, _ = env
+    p = rand_params(12)
+    m, mu, sig, osc = scaled_mlp(sme, p, seed=3)
+    rng = np.random.default_rng(13)
+    x = (rng.standard_normal((1000, 9)) * 2.0 + 0.5).astype(np.float32)
+    t = rng.standard_normal((1000, 2)).astype(np.float32)
+    idx = rng.permutation(1000)[:300].astype(np.int64)
+    loss, g = m.loss_grad(torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda(), idx=torch.from_numpy(idx).cuda())
+    xn = ((x[idx] - mu) * (np.float32(1.0) / sig)).astype(np.float64)
+    tn = (t[idx] / osc).astype(np.float64)
+    lref, gref = omlp.loss_grad(p.astype(np.float64), xn, tn)
+    assert loss == pytest.approx(lref, rel=1e-5)
+    assert np.max(np.abs(g.cpu().numpy() - gref)) <= 1e-4 * np.max(np.abs(gref))
+    y = m.forward(torch.from_numpy(x).cuda()).cpu().numpy()
+    yref, _ = omlp.forward(p.astype(np.float64), ((x - mu) * (np.float32(1.0) / sig)).astype(np.float64))
+    np.testing.assert_allclose(y, yref, rtol=0, atol=2e-5 * max(1.0, np.abs(yref).max()))
+    m.close()
+
+
+def test_training_is_deterministic(env):
+    torch, sme, closure = env
+    feat, targ = closure.generate(range(1000, 1002), n=256, steps=60, every=3, cells_per_snapshot=64)
+    out = []
+    for _ in range(2):
+        mlp, sc, hist = closure.fit(feat, targ, epochs=2, batch=512, seed=5)
+        out.append((mlp.get_params(), hist))
+        mlp.close()
+    assert np.array_equal(out[0][0], out[1][0]) and out[0][1] == out[1][1]
+
+
 def test_samples_match_oracle(env):
     torch, sme, _ = env
     p8 = W.smooth_1d(n=512, level=8, seed=1001, steps=30)
