@@ -21,6 +21,10 @@ FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
          # no packed FP32 instructions anywhere in the device code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-pass-failed", "-fconstexpr-steps=100000000",
+         # only the explicit fma() calls fuse: the same source gives the same
+         # rounding in every kernel it is inlined into (a grid advanced in an
+         # ensemble stays bitwise equal to the same grid advanced alone)
+         "-ffp-contract=off",
          # keep constant materialisation next to its use: hoisting hundreds of
          # FP64 tensor literals out of the row loop only spills them
          "-mllvm", "-disable-machine-licm"]

@@ -23,6 +23,10 @@ __global__ __launch_bounds__(kBlock) void k_batch_step(BatchArgs B)
     const int lane = threadIdx.x & (kWave - 1);
     const int nwaves = (int)gridDim.x * (kBlock / kWave);
     const int w = __builtin_amdgcn_readfirstlane((int)blockIdx.x * (kBlock / kWave) + (int)(threadIdx.x >> 6));
+    // one staging area per wave, sized for the highest level of the ensemble
+    constexpr int sd = stage_doubles<kBatchMaxLevel>();
+    __shared__ __attribute__((aligned(16))) double stage_all[(kBlock / kWave) * sd];
+    double *const stage = stage_all + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) * sd;
     for (int it = w; it < B.nitems; it += nwaves) {
         const BatchItem item = B.items[it];
         const BatchInst I = B.inst[item.inst];
@@ -62,11 +66,11 @@ __global__ __launch_bounds__(kBlock) void k_batch_step(BatchArgs B)
         if (item.sx == 0 && item.sy == 0 && lane == 0) slot_update(a, dt);
         double r = 0.0;
         switch (I.level) {
-        case 0: r = band2d<0>(a, dt, item.sx, item.sy); break;
-        case 1: r = band2d<1>(a, dt, item.sx, item.sy); break;
-        case 2: r = band2d<2>(a, dt, item.sx, item.sy); break;
-        case 3: r = band2d<3>(a, dt, item.sx, item.sy); break;
-        case 4: r = band2d<4>(a, dt, item.sx, item.sy); break;
+        case 0: r = band2d<0>(a, dt, item.sx, item.sy, stage); break;
+        case 1: r = band2d<1>(a, dt, item.sx, item.sy, stage); break;
+        case 2: r = band2d<2>(a, dt, item.sx, item.sy, stage); break;
+        case 3: r = band2d<3>(a, dt, item.sx, item.sy, stage); break;
+        case 4: r = band2d<4>(a, dt, item.sx, item.sy, stage); break;
         default: break;
         }
         r = wave_max(r);

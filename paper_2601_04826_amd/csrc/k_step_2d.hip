@@ -9,8 +9,15 @@ using namespace detail;
 
 namespace {
 
+// resident waves per SIMD the register allocation aims for, per level
+template <int N>
+constexpr int waves_target()
+{
+    return N == 2 ? 3 : (N == 4 ? 2 : 1);
+}
+
 template <int N, bool CLOS>
-__global__ __launch_bounds__(kBlock) void k_step_2d(StepArgs a)
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(waves_target<N>()))) void k_step_2d(StepArgs a)
 {
     const double dt = step_dt(a);
     if (blockIdx.x == 0 && threadIdx.x == 0) slot_update(a, dt);
@@ -26,10 +33,13 @@ __global__ __launch_bounds__(kBlock) void k_step_2d(StepArgs a)
     const int nblk = (int)gridDim.x;
     const int per_xcd = (nblk + kXcd - 1) / kXcd;
     const int slot = (int)(blockIdx.x % kXcd) * per_xcd + (int)(blockIdx.x / kXcd);
-    const int wave = slot * (kBlock / kWave) + (threadIdx.x >> 6);
+    // wave-uniform (scalar) band coordinates: the staged loads need uniform row addresses
+    const int wave = __builtin_amdgcn_readfirstlane(slot * (kBlock / kWave) + (int)(threadIdx.x >> 6));
+    constexpr int sd = stage_doubles<N>();
+    __shared__ __attribute__((aligned(16))) double stage[(kBlock / kWave) * (sd > 0 ? sd : 1)];
     double rmax = 0.0;
     if (wave < nsx * nsy)  // waves beyond the grid only join the reduction
-        rmax = band2d<N, CLOS>(a, dt, wave % nsx, wave / nsx);
+        rmax = band2d<N, CLOS>(a, dt, wave % nsx, wave / nsx, stage + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) * sd);
     publish_ratio(a.slots[a.sb], rmax);
 }
 

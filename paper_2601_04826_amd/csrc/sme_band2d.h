@@ -10,8 +10,12 @@
 //   * the y-face between the previous and the current row is computed once,
 //     with the previous row held in registers (two register sets that swap
 //     roles every row, so nothing is copied);
-//   * rows are loaded one at a time (registers go to occupancy rather than to
-//     a prefetched row).
+//   * up to level kStageMaxLevel, rows reach registers through LDS: the loads of
+//     row j + 1 go straight from memory into one of two per-wave LDS row
+//     buffers (buffer loads with the LDS destination, one 4-byte word per
+//     lane) while row j is computed, so the next row is in flight during the
+//     arithmetic without holding registers; higher levels load each row into
+//     registers when it is needed.
 // With a learned closure (CLOS, level 1) each finished cell also adds dt times
 // the network's correction rates, computed from Q^n by the rates pass.
 // Every face value is computed from the same inputs by the same code whichever
@@ -66,6 +70,87 @@ __device__ __forceinline__ void load_row(const StepArgs &a, int j, int col, bool
     bool my;
     const int row = ghost_index(j, a.ny, a.bc[2], a.bc[3], my);
     load_raw<N>(a, row, my, col, mx, r);
+}
+
+// ---- row staging through LDS
+constexpr int kStageMaxLevel = 5;
+
+// doubles of one wave's staging area: two row buffers of (h, b, qx_0..qx_N,
+// qy_0..qy_N), 64 columns each
+template <int N>
+constexpr int stage_doubles()
+{
+    return N <= kStageMaxLevel ? 2 * (2 * (N + 1) + 2) * kWave : 0;
+}
+
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+// Per-lane byte offsets, within a row, of the two 4-byte words a lane stages:
+// word w = 64 h + lane of a field row is half (lane & 1) of the double in
+// column c0 + 32 h + lane / 2 (c0 = first column of the wave, ghosts mapped).
+__device__ __forceinline__ void stage_offsets(const StepArgs &a, int c0, unsigned *voff)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        bool m;
+        const int col = ghost_index(c0 + 32 * h + (lane >> 1), a.nx, a.bc[0], a.bc[1], m);
+        voff[h] = (unsigned)col * 8u + 4u * (unsigned)(lane & 1);
+    }
+}
+
+// Issue the loads of row j (ghost rows mapped) into a row buffer: field f of
+// the row lands at buf[f * 64 + column - c0].  Returns at once; wait_staged()
+// makes the data visible.
+template <int N>
+__device__ __forceinline__ void stage_row(const StepArgs &a, int j, const unsigned *voff, double *buf)
+{
+    constexpr int n = N + 1;
+    bool my;
+    const int row = ghost_index(j, a.ny, a.bc[2], a.bc[3], my);
+    const int64_t r0 = (int64_t)row * a.nx;
+    const int bytes = a.nx * 8;
+    auto one = [&](const double *base, int f) {
+        const __amdgpu_buffer_rsrc_t rs =
+            __builtin_amdgcn_make_buffer_rsrc((void *)(base + r0), (short)0, bytes, 0x00020000);
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void_t *)(buf + f * kWave + 32 * h), 4, voff[h], 0, 0,
+                                                     0);
+    };
+    one(a.q, 0);
+    one(a.b, 1);
+#pragma unroll
+    for (int k = 0; k < n; ++k) {
+        one(a.q + (1 + k) * a.stride, 2 + k);
+        one(a.q + (1 + n + k) * a.stride, 2 + n + k);
+    }
+}
+
+// Every staged row (and every store) of this wave has landed.  Written as an
+// asm statement with a memory clobber: the compiler does not track the LDS
+// destination of these loads, and the intrinsic form of the wait is not a
+// memory barrier, so the reads of a staged row could otherwise be scheduled
+// before it.
+__device__ __forceinline__ void wait_staged() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+// row j from a row buffer into registers, with this lane's mirrors
+template <int N>
+__device__ __forceinline__ void read_row(const StepArgs &a, int j, bool mx, const double *buf, Raw2<N> &r)
+{
+    constexpr int n = N + 1;
+    bool my;
+    (void)ghost_index(j, a.ny, a.bc[2], a.bc[3], my);
+    const int lane = threadIdx.x & (kWave - 1);
+    r.h = buf[lane];
+    r.b = buf[kWave + lane];
+#pragma unroll
+    for (int k = 0; k < n; ++k) {
+        const double vx = buf[(2 + k) * kWave + lane];
+        const double vy = buf[(2 + n + k) * kWave + lane];
+        r.qx[k] = mx ? -vx : vx;
+        r.qy[k] = my ? -vy : vy;
+    }
 }
 
 template <int N>
@@ -256,9 +341,11 @@ __device__ __forceinline__ void close_band(const StepArgs &a, double dt, Cell2<N
 }
 
 // Whole band (strip sx, band sy) of one grid: returns the largest CFL ratio
-// of the cells it wrote.  All 64 lanes of the wave must call it.
+// of the cells it wrote.  All 64 lanes of the wave must call it.  stage is
+// this wave's staging area (stage_doubles<N>() doubles of LDS) for levels up
+// to kStageMaxLevel, unused above.
 template <int N, bool CLOS = false>
-__device__ __forceinline__ double band2d(const StepArgs &a, double dt, int sx, int sy)
+__device__ __forceinline__ double band2d(const StepArgs &a, double dt, int sx, int sy, double *stage)
 {
     constexpr int n = N + 1;
     constexpr int nf = 2 * n + 1;
@@ -272,27 +359,64 @@ __device__ __forceinline__ double band2d(const StepArgs &a, double dt, int sx, i
     double rmax = 0.0;
     Cell2<N> A, B;
     double accA[nf], accB[nf];
-    Raw2<N> nxt;
-    load_row<N>(a, j0 - 1, col, mx, nxt);
-    cell_flux<N>(A, nxt, a.g);  // halo row below the band
 #pragma unroll
     for (int f = 0; f < nf; ++f) accA[f] = 0.0;
-    load_row<N>(a, j0, col, mx, nxt);
-    int j = j0;
-    while (true) {
-        Raw2<N> cur = nxt;
-        row<N, CLOS>(a, dt, A, accA, B, accB, cur, j, c, outc, j > j0, rmax);
-        load_row<N>(a, j + 1, col, mx, nxt);
-        if (++j == j1) {
-            close_band<N, CLOS>(a, dt, B, accB, A, nxt, j1, c, outc, rmax);
-            break;
+    if constexpr (N <= kStageMaxLevel) {
+        (void)col;
+        constexpr int rowd = (2 * n + 2) * kWave;  // doubles of one row buffer
+        double *const buf0 = stage, *const buf1 = stage + rowd;
+        unsigned voff[2];
+        stage_offsets(a, sx * kOut - 1, voff);
+        Raw2<N> cur;
+        stage_row<N>(a, j0 - 1, voff, buf0);
+        stage_row<N>(a, j0, voff, buf1);
+        wait_staged();
+        read_row<N>(a, j0 - 1, mx, buf0, cur);
+        cell_flux<N>(A, cur, a.g);  // halo row below the band
+        int j = j0;                 // row j is staged in buf1
+        while (true) {
+            // buf0's previous row was read into registers before its arithmetic
+            read_row<N>(a, j, mx, buf1, cur);
+            stage_row<N>(a, j + 1, voff, buf0);  // next row, or the closing halo row
+            row<N, CLOS>(a, dt, A, accA, B, accB, cur, j, c, outc, j > j0, rmax);
+            wait_staged();
+            if (++j == j1) {
+                read_row<N>(a, j1, mx, buf0, cur);
+                close_band<N, CLOS>(a, dt, B, accB, A, cur, j1, c, outc, rmax);
+                break;
+            }
+            read_row<N>(a, j, mx, buf0, cur);
+            stage_row<N>(a, j + 1, voff, buf1);
+            row<N, CLOS>(a, dt, B, accB, A, accA, cur, j, c, outc, true, rmax);
+            wait_staged();
+            if (++j == j1) {
+                read_row<N>(a, j1, mx, buf1, cur);
+                close_band<N, CLOS>(a, dt, A, accA, B, cur, j1, c, outc, rmax);
+                break;
+            }
         }
-        cur = nxt;
-        row<N, CLOS>(a, dt, B, accB, A, accA, cur, j, c, outc, true, rmax);
-        load_row<N>(a, j + 1, col, mx, nxt);
-        if (++j == j1) {
-            close_band<N, CLOS>(a, dt, A, accA, B, nxt, j1, c, outc, rmax);
-            break;
+    } else {
+        (void)stage;
+        Raw2<N> nxt;
+        load_row<N>(a, j0 - 1, col, mx, nxt);
+        cell_flux<N>(A, nxt, a.g);  // halo row below the band
+        load_row<N>(a, j0, col, mx, nxt);
+        int j = j0;
+        while (true) {
+            Raw2<N> cur = nxt;
+            row<N, CLOS>(a, dt, A, accA, B, accB, cur, j, c, outc, j > j0, rmax);
+            load_row<N>(a, j + 1, col, mx, nxt);
+            if (++j == j1) {
+                close_band<N, CLOS>(a, dt, B, accB, A, nxt, j1, c, outc, rmax);
+                break;
+            }
+            cur = nxt;
+            row<N, CLOS>(a, dt, B, accB, A, accA, cur, j, c, outc, true, rmax);
+            load_row<N>(a, j + 1, col, mx, nxt);
+            if (++j == j1) {
+                close_band<N, CLOS>(a, dt, A, accA, B, nxt, j1, c, outc, rmax);
+                break;
+            }
         }
     }
     return rmax;

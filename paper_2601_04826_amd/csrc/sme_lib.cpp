@@ -676,7 +676,17 @@ int sme_run(sme_ctx *c, int64_t n_steps, double t_end, double *t_out, int64_t *s
             ++k;
         }
     }
-    while (left-- > 0) HIPCHK(c, launch_one_step(c, 0.0, te));
+    // single launches (the remainder, or every step without graphs): with an
+    // end time, look at the device clock after every kGraphSteps steps
+    for (int64_t k = 1; left > 0; ++k, --left) {
+        HIPCHK(c, launch_one_step(c, 0.0, te));
+        if (te > 0.0 && left > 1 && k % kGraphSteps == 0) {
+            Slot s;
+            int rr = read_slot(c, &s, nullptr);
+            if (rr) return rr;
+            if (s.t >= te) break;
+        }
+    }
     if (t_out || steps_done) {
         Slot s;
         ErrWord e;
