@@ -65,6 +65,21 @@ def test_layout_and_validation(sme):
     assert sme.sme_layout(2, t) == (7, 1)
 
 
+@pytest.mark.parametrize("mesh", [
+    dict(kind="1d", nx=0, x0=0, x1=1, bc=("wall", "wall")),
+    dict(kind="1d", nx=5, x0=1, x1=1, bc=("wall", "wall")),
+    dict(kind="2d", nx=0, ny=4, x0=0, x1=1, y0=0, y1=1, bc=("wall",) * 4),
+    dict(kind="2d", nx=4, ny=0, x0=0, x1=1, y0=0, y1=1, bc=("wall",) * 4),
+    dict(kind="2d", nx=4, ny=4, x0=0, x1=1, y0=1, y1=0, bc=("wall",) * 4),
+    dict(kind="2d", nx=4, ny=4, x0=0, x1=1, y0=0, y1=1, bc=("wall", "wall", "periodic", "wall")),
+])
+def test_layout_rejects_empty_and_invalid_meshes(sme, mesh):
+    m, _ = sme.make_mesh(mesh)
+    with pytest.raises(sme.SmeError) as e:
+        sme.sme_layout(1, m)
+    assert e.value.code == sme.SME_EINVAL
+
+
 def test_strerror(sme):
     assert sme.lib().sme_strerror(sme.SME_ENONPHYS) == b"non-physical state"
     assert sme.lib().sme_strerror(0) == b"ok"

@@ -132,6 +132,52 @@ def test_quadrature_points(sme, quad):
     assert rel_linf(q_gpu, q_orc) <= 1e-10
 
 
+def tiny_problem(kind, shape, bc, level=2, seed=0):
+    """Random smooth-ish state on a tiny grid (every field nonzero)."""
+    rng = np.random.default_rng(seed)
+    if kind == "1d":
+        n = shape
+        q = np.zeros((W.nfields(level, 1), n))
+        q[0] = rng.uniform(0.8, 1.5, n)
+        for k in range(level + 1):
+            q[1 + k] = q[0] * rng.uniform(-0.4, 0.4, n) / (k + 1)
+        return W._problem("1d", level, n, q, rng.uniform(0, 0.05, n), 30, nx=n, ny=1, x0=0.0, x1=1.0,
+                          y0=0.0, y1=1.0, bc=(bc, bc, "periodic", "periodic"))
+    nx, ny = shape
+    q = W.random_state_2d(level, nx * ny, seed)
+    return W._problem("2d", level, nx * ny, q, rng.uniform(0, 0.05, nx * ny), 30, nx=nx, ny=ny, x0=0.0,
+                      x1=nx / 10.0, y0=0.0, y1=ny / 10.0, bc=(bc,) * 4)
+
+
+@pytest.mark.parametrize("case", [("1d", 1, "periodic"), ("1d", 1, "wall"), ("1d", 2, "extrap"),
+                                  ("1d", 62, "periodic"), ("1d", 63, "wall"), ("1d", 64, "periodic"),
+                                  ("2d", (1, 1), "periodic"), ("2d", (1, 5), "wall"), ("2d", (5, 1), "periodic"),
+                                  ("2d", (62, 1), "extrap"), ("2d", (63, 2), "wall"), ("2d", (2, 63), "periodic")])
+def test_tiny_and_degenerate_grids(sme, case):
+    """Grids of one cell, one row or one column, and sizes around one wave's 62
+    outputs: 30 CFL steps against the oracle."""
+    kind, shape, bc = case
+    p = tiny_problem(kind, shape, bc)
+    q_gpu, q_orc, t_gpu, t_orc = run_both(sme, p, 30)
+    # Between two walls one cell apart the normal momenta decay to 1e-18 of
+    # their start: each field is measured against the larger of its final and
+    # its initial maximum, the size of the values the rounding happened on.
+    scale = np.maximum(np.abs(q_orc).max(axis=1), np.abs(p["q"]).max(axis=1))
+    assert np.max(np.abs(q_gpu - q_orc).max(axis=1) / scale) <= 1e-10
+    assert abs(t_gpu - t_orc) <= 1e-12 * t_orc
+
+
+@pytest.mark.parametrize("ntri", [1, 2])
+def test_one_and_two_triangles(sme, ntri):
+    vert = np.array([[0.0, 0.0], [1.0, 0.0], [1.0, 1.0], [0.0, 1.0]])
+    tri = np.array([[0, 1, 2], [0, 2, 3]], dtype=np.int32)[:ntri]
+    level = 2
+    q = W.random_state_2d(level, ntri, 5)
+    p = W._problem("tri", level, ntri, q, np.array([0.0, 0.03])[:ntri], 30, vert=vert, tri=tri, bc=("wall",) * 4)
+    q_gpu, q_orc, _, _ = run_both(sme, p, 30)
+    assert rel_linf(q_gpu, q_orc) <= 1e-10
+
+
 def test_single_step_fixed_dt(sme):
     vert, tri = W.delaunay_unit_square(3000, seed=3)
     q = W.random_state_2d(2, len(tri), seed=4)
