@@ -124,14 +124,14 @@ class ClosureSolver:
     """Level 1 + closure on a 1D or structured grid, with the plain level-8
     solver as fallback once a cell's features leave the training range."""
 
-    def __init__(self, problem8, mlp, chunk=50, stream=None, max_out_of_range=1e-3):
+    def __init__(self, problem8, mlp, chunk=50, stream=None, max_out_of_range=1e-3, precision="fp32"):
         self.p8 = problem8
         self.mlp = mlp
         self.chunk = chunk
         self.max_oor = max_out_of_range  # tolerated fraction of out-of-range cell-steps
         self.stream = stream
         self.s1 = sme.Solver(_project_any(problem8), stream=stream)
-        self.s1.attach_closure(mlp)
+        self.s1.attach_closure(mlp, precision=precision)
         self.s8 = None
         self.fell_back_at = None
 

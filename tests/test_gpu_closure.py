@@ -375,6 +375,50 @@ def test_out_of_range_flag(env, precision):
     s.close()
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp16"])
+def test_closure_solver_falls_back_to_level8(env, precision):
+    """A network trusted nowhere: the first chunk already leaves the training
+    box, so the run restarts with plain level 8 from the lifted state."""
+    torch, sme, closure = env
+    p8 = W.smooth_1d(n=256, level=8, seed=1012)
+    m = sme.MLP(rand_params(14))
+    m.set_scaling(np.zeros(9), np.ones(9), np.ones(2), np.full(9, 1e3), np.full(9, 2e3))
+    cs = closure.ClosureSolver(p8, m, chunk=20, precision=precision)
+    cs.set_state(p8["q"])
+    out = cs.run_to(0.05)
+    assert cs.fell_back_at == 0.0
+    cs.close()
+    s8 = sme.Solver(p8)
+    s8.set_state(closure._lift_state(closure._project_state(p8["q"], p8), p8))
+    s8.run(10 ** 6, t_end=0.05)
+    assert np.array_equal(out, s8.get_state())
+    s8.close()
+    m.close()
+
+
+def test_closure_solver_in_range_runs_level1(env):
+    """A zero network trusted everywhere: no fallback, and chunked runs equal
+    one uninterrupted level-1 run (up to the last step of each chunk, which
+    lands on the end time from a fresh clock)."""
+    torch, sme, closure = env
+    p8 = W.smooth_1d(n=256, level=8, seed=1013)
+    m = sme.MLP(np.zeros(omlp.NPARAM, dtype=np.float32))
+    cs = closure.ClosureSolver(p8, m, chunk=25)
+    cs.set_state(p8["q"])
+    out = cs.run_to(0.05)
+    assert cs.fell_back_at is None
+    cs.close()
+    p1 = dict(p8, level=1, q=closure._project_state(p8["q"], p8))
+    s1 = sme.Solver(p1)
+    s1.set_state(p1["q"])
+    s1.run(10 ** 6, t_end=0.05)
+    ref = closure._lift_state(s1.get_state(), p8)
+    s1.close()
+    np.testing.assert_allclose(out, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+    assert np.all(out[3:] == 0.0)
+    m.close()
+
+
 def test_trained_closure_gain_on_held_out_seeds(env):
     """Train on level-8 runs the solver generates (seeds 1000..1023), then on
     held-out seeds compare level 1 + closure and plain level 1 against level 8
