@@ -213,8 +213,10 @@ __device__ __forceinline__ void y_side(const Cell2<N> &c, Side<N, true> &s)
 }
 
 // y-face between P (below) and C (above), normal +y.  Adds P's share to accP
-// and sets accC to C's share; both in physical field order, scaled by 1/dy.
-template <int N>
+// (if add_p) and, if SET_C, sets accC to C's share; both in physical field
+// order, scaled by 1/dy.  (A compile-time flag rather than a null accC: a
+// pointer test keeps the accumulator array in scratch memory at higher levels.)
+template <int N, bool SET_C>
 __device__ __forceinline__ void y_face(const StepArgs &a, const Cell2<N> &P, const Cell2<N> &C, double *accP,
                                        double *accC, bool add_p)
 {
@@ -233,7 +235,7 @@ __device__ __forceinline__ void y_face(const StepArgs &a, const Cell2<N> &P, con
             accP[1 + k] = fma(a.idy, fma(0.5, D[1 + n + k], Fh[1 + n + k]), accP[1 + k]);
         }
     }
-    if (accC) {
+    if constexpr (SET_C) {
         accC[0] = a.idy * fma(0.5, D[0], -Fh[0]);
 #pragma unroll
         for (int k = 0; k < n; ++k) {
@@ -324,7 +326,7 @@ __device__ __forceinline__ void row(const StepArgs &a, double dt, Cell2<N> &P, d
                                     double &rmax)
 {
     cell_flux<N>(C, raw, a.g);
-    y_face<N>(a, P, C, accP, accC, finish_p);
+    y_face<N, true>(a, P, C, accP, accC, finish_p);
     if (finish_p) rmax = fmax(rmax, finish_cell<N, CLOS>(a, dt, (int64_t)(j - 1) * a.nx + c, outc, P, accP));
     x_faces<N>(a, C, accC);
 }
@@ -336,7 +338,7 @@ __device__ __forceinline__ void close_band(const StepArgs &a, double dt, Cell2<N
                                            double &rmax)
 {
     cell_flux<N>(G, raw, a.g);
-    y_face<N>(a, P, G, accP, nullptr, true);
+    y_face<N, false>(a, P, G, accP, nullptr, true);
     rmax = fmax(rmax, finish_cell<N, CLOS>(a, dt, (int64_t)(j1 - 1) * a.nx + c, outc, P, accP));
 }
 
