@@ -88,6 +88,37 @@ def test_batch_bitwise_equals_single_grid(sme):
     bt.close()
 
 
+def tiny_grid(nx, ny, level, bc, seed):
+    rng = np.random.default_rng(seed)
+    q = W.random_state_2d(level, nx * ny, seed)
+    return W._problem("2d", level, nx * ny, q, rng.uniform(0, 0.05, nx * ny), 30, nx=nx, ny=ny, x0=0.0,
+                      x1=nx / 10.0, y0=0.0, y1=ny / 10.0, bc=(bc,) * 4)
+
+
+def test_batch_tiny_grids_bitwise_equal_single_grid(sme):
+    """One-cell, one-row, one-column and wave-edge grids (62, 63, 124 columns)
+    mixed with larger ones in one ensemble: each grid bitwise equal to the
+    same grid advanced alone, with the same clock."""
+    shapes = [(1, 1), (1, 7), (7, 1), (62, 3), (63, 2), (124, 5), (2, 63), (130, 40), (64, 64)]
+    bcs = ["periodic", "wall", "extrap"]
+    probs = [tiny_grid(nx, ny, k % 5, bcs[k % 3], 300 + k) for k, (nx, ny) in enumerate(shapes)]
+    print("tiny ensemble:", [(p["nx"], p["ny"], p["level"], p["bc"][0]) for p in probs], flush=True)
+    bt = sme.Batch(probs)
+    for i, p in enumerate(probs):
+        bt.set_state(i, p["q"])
+    bt.run(30)
+    for i, p in enumerate(probs):
+        s = sme.Solver(p)
+        s.set_state(p["q"])
+        t1, n1 = s.run(30)
+        q1 = s.get_state()
+        s.close()
+        assert n1 == 30
+        assert np.array_equal(bt.get_state(i), q1), (i, p["nx"], p["ny"], p["level"])
+        assert bt.time(i)[0] == t1
+    bt.close()
+
+
 def test_batch_autotune_and_cache(sme, tmp_path):
     probs = small_batch(n=8, seed=90)
     bt = sme.Batch(probs)
