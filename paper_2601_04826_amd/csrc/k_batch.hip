@@ -87,10 +87,13 @@ hipError_t launch_batch_step(const BatchArgs &a, int grid, hipStream_t s)
     return hipGetLastError();
 }
 
-int batch_vgprs()
+// resident waves per SIMD of the ensemble kernel (runtime occupancy query:
+// VGPRs, AGPRs and LDS together; a block is one wave per SIMD); 1 on failure
+int batch_waves_per_simd()
 {
-    hipFuncAttributes fa{};
-    return hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(&k_batch_step)) == hipSuccess ? fa.numRegs : -1;
+    int blocks = 0;
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch_step, kBlock, 0);
+    return e == hipSuccess && blocks > 0 ? blocks * (kBlock / kWave) / 4 : 1;
 }
 
 }  // namespace sme

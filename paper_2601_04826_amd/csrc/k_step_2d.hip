@@ -36,7 +36,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(waves_ta
     // wave-uniform (scalar) band coordinates: the staged loads need uniform row addresses
     const int wave = __builtin_amdgcn_readfirstlane(slot * (kBlock / kWave) + (int)(threadIdx.x >> 6));
     constexpr int sd = stage_doubles<N>();
-    __shared__ __attribute__((aligned(16))) double stage[(kBlock / kWave) * (sd > 0 ? sd : 1)];
+    __shared__ __attribute__((aligned(16))) double stage[(kBlock / kWave) * sd];
     double rmax = 0.0;
     if (wave < nsx * nsy)  // waves beyond the grid only join the reduction
         rmax = band2d<N, CLOS>(a, dt, wave % nsx, wave / nsx, stage + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) * sd);
@@ -63,25 +63,28 @@ hipError_t launch_step_2d(int level, const StepArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
-int step_2d_vgprs(int level)
+// resident waves per SIMD of the structured step kernel at this level, from
+// the runtime's occupancy calculation (VGPRs, AGPRs and LDS together); a block
+// is one wave per SIMD.  1 if the query fails.
+int step_2d_waves_per_simd(int level)
 {
-    hipFuncAttributes fa{};
+    int blocks = 0;
     hipError_t e = hipErrorInvalidValue;
-#define A2(N) e = hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(&k_step_2d<N, false>))
+#define O2(N) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_step_2d<N, false>, kBlock, 0)
     switch (level) {
-    case 0: A2(0); break;
-    case 1: A2(1); break;
-    case 2: A2(2); break;
-    case 3: A2(3); break;
-    case 4: A2(4); break;
-    case 5: A2(5); break;
-    case 6: A2(6); break;
-    case 7: A2(7); break;
-    case 8: A2(8); break;
+    case 0: O2(0); break;
+    case 1: O2(1); break;
+    case 2: O2(2); break;
+    case 3: O2(3); break;
+    case 4: O2(4); break;
+    case 5: O2(5); break;
+    case 6: O2(6); break;
+    case 7: O2(7); break;
+    case 8: O2(8); break;
     default: break;
     }
-#undef A2
-    return e == hipSuccess ? fa.numRegs : -1;
+#undef O2
+    return e == hipSuccess && blocks > 0 ? blocks * (kBlock / kWave) / 4 : 1;
 }
 
 }  // namespace sme

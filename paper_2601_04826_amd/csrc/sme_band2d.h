@@ -10,12 +10,11 @@
 //   * the y-face between the previous and the current row is computed once,
 //     with the previous row held in registers (two register sets that swap
 //     roles every row, so nothing is copied);
-//   * up to level kStageMaxLevel, rows reach registers through LDS: the loads of
-//     row j + 1 go straight from memory into one of two per-wave LDS row
-//     buffers (buffer loads with the LDS destination, one 4-byte word per
-//     lane) while row j is computed, so the next row is in flight during the
-//     arithmetic without holding registers; higher levels load each row into
-//     registers when it is needed.
+//   * rows reach registers through LDS: the loads of row j + 1 go straight
+//     from memory into one of two per-wave LDS row buffers (buffer loads with
+//     the LDS destination, one 4-byte word per lane) while row j is computed,
+//     so the next row is in flight during the arithmetic without holding
+//     registers.
 // With a learned closure (CLOS, level 1) each finished cell also adds dt times
 // the network's correction rates, computed from Q^n by the rates pass.
 // Every face value is computed from the same inputs by the same code whichever
@@ -48,39 +47,14 @@ struct Raw2 {
     double qx[N + 1], qy[N + 1];
 };
 
-template <int N>
-__device__ __forceinline__ void load_raw(const StepArgs &a, int row, bool my, int col, bool mx, Raw2<N> &r)
-{
-    constexpr int n = N + 1;
-    const int64_t cell = (int64_t)row * a.nx + col;
-    r.h = a.q[cell];
-    r.b = a.b[cell];
-#pragma unroll
-    for (int k = 0; k < n; ++k) {
-        const double vx = a.q[(1 + k) * a.stride + cell];
-        const double vy = a.q[(1 + n + k) * a.stride + cell];
-        r.qx[k] = mx ? -vx : vx;
-        r.qy[k] = my ? -vy : vy;
-    }
-}
-
-template <int N>
-__device__ __forceinline__ void load_row(const StepArgs &a, int j, int col, bool mx, Raw2<N> &r)
-{
-    bool my;
-    const int row = ghost_index(j, a.ny, a.bc[2], a.bc[3], my);
-    load_raw<N>(a, row, my, col, mx, r);
-}
-
 // ---- row staging through LDS
-constexpr int kStageMaxLevel = 5;
 
 // doubles of one wave's staging area: two row buffers of (h, b, qx_0..qx_N,
 // qy_0..qy_N), 64 columns each
 template <int N>
 constexpr int stage_doubles()
 {
-    return N <= kStageMaxLevel ? 2 * (2 * (N + 1) + 2) * kWave : 0;
+    return 2 * (2 * (N + 1) + 2) * kWave;
 }
 
 typedef __attribute__((address_space(3))) void lds_void_t;
@@ -344,81 +318,54 @@ __device__ __forceinline__ void close_band(const StepArgs &a, double dt, Cell2<N
 
 // Whole band (strip sx, band sy) of one grid: returns the largest CFL ratio
 // of the cells it wrote.  All 64 lanes of the wave must call it.  stage is
-// this wave's staging area (stage_doubles<N>() doubles of LDS) for levels up
-// to kStageMaxLevel, unused above.
+// this wave's staging area (stage_doubles<N>() doubles of LDS).
 template <int N, bool CLOS = false>
 __device__ __forceinline__ double band2d(const StepArgs &a, double dt, int sx, int sy, double *stage)
 {
     constexpr int n = N + 1;
     constexpr int nf = 2 * n + 1;
+    constexpr int rowd = (2 * n + 2) * kWave;  // doubles of one row buffer
     const int lane = threadIdx.x & (kWave - 1);
     const int c = sx * kOut - 1 + lane;
     const int j0 = sy * a.rows;
     const int j1 = min(j0 + a.rows, a.ny);
-    bool mx;
-    const int col = ghost_index(c, a.nx, a.bc[0], a.bc[1], mx);
+    bool mx;  // this lane's column is a wall ghost: its x momenta are mirrored
+    (void)ghost_index(c, a.nx, a.bc[0], a.bc[1], mx);
     const bool outc = lane >= 1 && lane <= kOut && c < a.nx;
     double rmax = 0.0;
     Cell2<N> A, B;
     double accA[nf], accB[nf];
 #pragma unroll
     for (int f = 0; f < nf; ++f) accA[f] = 0.0;
-    if constexpr (N <= kStageMaxLevel) {
-        (void)col;
-        constexpr int rowd = (2 * n + 2) * kWave;  // doubles of one row buffer
-        double *const buf0 = stage, *const buf1 = stage + rowd;
-        unsigned voff[2];
-        stage_offsets(a, sx * kOut - 1, voff);
-        Raw2<N> cur;
-        stage_row<N>(a, j0 - 1, voff, buf0);
-        stage_row<N>(a, j0, voff, buf1);
+    double *const buf0 = stage, *const buf1 = stage + rowd;
+    unsigned voff[2];
+    stage_offsets(a, sx * kOut - 1, voff);
+    Raw2<N> cur;
+    stage_row<N>(a, j0 - 1, voff, buf0);
+    stage_row<N>(a, j0, voff, buf1);
+    wait_staged();
+    read_row<N>(a, j0 - 1, mx, buf0, cur);
+    cell_flux<N>(A, cur, a.g);  // halo row below the band
+    int j = j0;                 // row j is staged in buf1
+    while (true) {
+        // buf0's previous row was read into registers before its arithmetic
+        read_row<N>(a, j, mx, buf1, cur);
+        stage_row<N>(a, j + 1, voff, buf0);  // next row, or the closing halo row
+        row<N, CLOS>(a, dt, A, accA, B, accB, cur, j, c, outc, j > j0, rmax);
         wait_staged();
-        read_row<N>(a, j0 - 1, mx, buf0, cur);
-        cell_flux<N>(A, cur, a.g);  // halo row below the band
-        int j = j0;                 // row j is staged in buf1
-        while (true) {
-            // buf0's previous row was read into registers before its arithmetic
-            read_row<N>(a, j, mx, buf1, cur);
-            stage_row<N>(a, j + 1, voff, buf0);  // next row, or the closing halo row
-            row<N, CLOS>(a, dt, A, accA, B, accB, cur, j, c, outc, j > j0, rmax);
-            wait_staged();
-            if (++j == j1) {
-                read_row<N>(a, j1, mx, buf0, cur);
-                close_band<N, CLOS>(a, dt, B, accB, A, cur, j1, c, outc, rmax);
-                break;
-            }
-            read_row<N>(a, j, mx, buf0, cur);
-            stage_row<N>(a, j + 1, voff, buf1);
-            row<N, CLOS>(a, dt, B, accB, A, accA, cur, j, c, outc, true, rmax);
-            wait_staged();
-            if (++j == j1) {
-                read_row<N>(a, j1, mx, buf1, cur);
-                close_band<N, CLOS>(a, dt, A, accA, B, cur, j1, c, outc, rmax);
-                break;
-            }
+        if (++j == j1) {
+            read_row<N>(a, j1, mx, buf0, cur);
+            close_band<N, CLOS>(a, dt, B, accB, A, cur, j1, c, outc, rmax);
+            break;
         }
-    } else {
-        (void)stage;
-        Raw2<N> nxt;
-        load_row<N>(a, j0 - 1, col, mx, nxt);
-        cell_flux<N>(A, nxt, a.g);  // halo row below the band
-        load_row<N>(a, j0, col, mx, nxt);
-        int j = j0;
-        while (true) {
-            Raw2<N> cur = nxt;
-            row<N, CLOS>(a, dt, A, accA, B, accB, cur, j, c, outc, j > j0, rmax);
-            load_row<N>(a, j + 1, col, mx, nxt);
-            if (++j == j1) {
-                close_band<N, CLOS>(a, dt, B, accB, A, nxt, j1, c, outc, rmax);
-                break;
-            }
-            cur = nxt;
-            row<N, CLOS>(a, dt, B, accB, A, accA, cur, j, c, outc, true, rmax);
-            load_row<N>(a, j + 1, col, mx, nxt);
-            if (++j == j1) {
-                close_band<N, CLOS>(a, dt, A, accA, B, nxt, j1, c, outc, rmax);
-                break;
-            }
+        read_row<N>(a, j, mx, buf0, cur);
+        stage_row<N>(a, j + 1, voff, buf1);
+        row<N, CLOS>(a, dt, B, accB, A, accA, cur, j, c, outc, true, rmax);
+        wait_staged();
+        if (++j == j1) {
+            read_row<N>(a, j1, mx, buf1, cur);
+            close_band<N, CLOS>(a, dt, A, accA, B, cur, j1, c, outc, rmax);
+            break;
         }
     }
     return rmax;

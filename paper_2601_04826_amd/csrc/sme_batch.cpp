@@ -125,7 +125,7 @@ int build_items(sme_batch *b)
     }
     BCHK(b, hipMemcpy(b->inst, tab.data(), tab.size() * sizeof(BatchInst), hipMemcpyHostToDevice));
     // persistent grid: every resident wave slot of the device, at most one wave per item
-    const int per_simd = host::waves_per_simd(batch_vgprs());
+    const int per_simd = batch_waves_per_simd();
     const int full = host::device_cus() * per_simd;  // blocks of 4 waves
     b->grid = std::max(1, std::min(full, (b->nitems + 3) / 4));
     drop_graphs(b);

@@ -57,15 +57,5 @@ inline int device_cus()
     return 256;
 }
 
-// resident waves per SIMD for a kernel using `regs` VGPRs per lane (512 per
-// lane of a SIMD, allocated in granules of 8)
-inline int waves_per_simd(int regs)
-{
-    if (regs <= 0) return 2;
-    const int r = (regs + 7) / 8 * 8;
-    const int w = 512 / r;
-    return w < 1 ? 1 : (w > 8 ? 8 : w);
-}
-
 }  // namespace host
 }  // namespace sme

@@ -111,12 +111,12 @@ struct BatchArgs {
 };
 
 hipError_t launch_batch_step(const BatchArgs &a, int grid, hipStream_t s);
-int batch_vgprs();
+int batch_waves_per_simd();  // resident waves per SIMD of the ensemble kernel
 
 // host-side launchers; level is 0..8
 hipError_t launch_step_1d(int level, const StepArgs &a, hipStream_t s);
 hipError_t launch_step_2d(int level, const StepArgs &a, hipStream_t s);
-int step_2d_vgprs(int level);  // registers per lane of the structured step kernel, -1 on error
+int step_2d_waves_per_simd(int level);  // resident waves per SIMD of the structured step kernel
 hipError_t launch_step_tri(int level, const StepArgs &a, hipStream_t s);
 hipError_t launch_eig(int dim, int kind, int level, const StepArgs &a, hipStream_t s);
 hipError_t launch_slots_reset(Slot *slots, ErrWord *err, int sa, hipStream_t s);  // err may be null

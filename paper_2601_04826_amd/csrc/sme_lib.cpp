@@ -264,7 +264,7 @@ std::vector<int64_t> rcm_order(const std::vector<int32_t> &nbr, int64_t n)
 int pick_rows(int level, int64_t nx, int64_t ny)
 {
     const int cus = host::device_cus();
-    const int per_simd = host::waves_per_simd(step_2d_vgprs(level));
+    const int per_simd = step_2d_waves_per_simd(level);
     const int64_t slots = (int64_t)cus * 4 * per_simd;
     const int64_t nsx = (nx + 61) / 62;
     int best = 8;
