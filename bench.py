@@ -26,6 +26,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFS = 78.6  # MI355X FP64 vector peak
 
 # Algorithmic bytes per cell-update of the step kernel: read every field of
 # Q^n and the bathymetry once, write every field of Q^{n+1} once.
@@ -44,6 +45,9 @@ WORKLOADS = {
     "dam_break_1d": dict(gen="dam_break_1d", args={}, kernel="k_step_1d", name="dam_break_1d_1000_level1"),
     "struct_2d_4096_l2": dict(gen="struct_2d", args=dict(n=4096), kernel="k_step_2d",
                               name="struct_2d_4096x4096_level2_periodic"),
+    # the closure's level-8 reference size: FP64-arithmetic heavy (roofline also against the FP64 peak)
+    "struct_2d_2048_l8": dict(gen="struct_2d", args=dict(n=2048, level=8), kernel="k_step_2d",
+                              name="struct_2d_2048x2048_level8_periodic"),
     "batch_512": dict(gen="batch", args={}, kernel="k_batch_step",
                       name="batch_512_grids_side64-512_levels1-4_walls"),
     "closure_2048": dict(gen="closure", args={}, kernel="k_closure_rates_mfma",
@@ -70,6 +74,20 @@ def load_traffic(workload, launches_bytes):
     if d.get("source_hash") != source_hash():
         return None
     return d.get("bytes_per_launch")
+
+
+def load_flops(workload):
+    """Executed FP64 flops per launch of the workload's kernel, from committed
+    rocprofv3 counter runs (SQ_INSTS_VALU_FLOPS_FP64) taken on the current
+    kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", f"flops_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("source_hash") != source_hash():
+        return None
+    return d.get("fp64_flops_per_launch")
 
 
 def cpu_baseline(problem, seconds=15.0):
@@ -205,6 +223,12 @@ def main():
                      "single_launch_us": per_launch_ms * 1e3},
         "cpu_baseline": None,
     }
+    flops = load_flops(args.workload)
+    if flops:
+        tf = flops / per_launch_s / 1e12
+        out["roofline"]["fp64"] = {"achieved": tf, "peak": FP64_PEAK_TFS, "unit": "TFLOP/s",
+                                   "frac": tf / FP64_PEAK_TFS, "flops_per_launch": flops,
+                                   "source": "executed FP64 flops per launch from rocprofv3 counters"}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(problem, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -1,0 +1,43 @@
+"""Host logic of bench.py (CPU): algorithmic bytes per cell, and the committed
+counter figures (HBM traffic, executed FP64 flops) that are reported only while
+the kernel sources still hash to the value they were taken on."""
+import json
+import os
+
+import bench
+
+
+def test_bytes_per_cell():
+    # read every field and the bathymetry once, write every field once
+    assert bench.bytes_per_cell("2d", 2) == (7 * 2 + 1) * 8 == 120
+    assert bench.bytes_per_cell("2d", 8) == (19 * 2 + 1) * 8 == 312
+    assert bench.bytes_per_cell("1d", 1) == (3 * 2 + 1) * 8 == 56
+    # triangles add 3 int32 neighbours and 3 x (n_x, n_y, |e|/|V|) FP64
+    assert bench.bytes_per_cell("tri", 3) == (9 * 2 + 1) * 8 + 12 + 72 == 236
+
+
+def test_counter_figures_follow_the_source_hash(tmp_path, monkeypatch):
+    csrc = tmp_path / "paper_2601_04826_amd" / "csrc"
+    csrc.mkdir(parents=True)
+    (csrc / "k.hip").write_text("// kernel v1\n")
+    (tmp_path / "profiles").mkdir()
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    h = bench.source_hash()
+    (tmp_path / "profiles" / "traffic_w.json").write_text(json.dumps({"source_hash": h, "bytes_per_launch": 123.0}))
+    (tmp_path / "profiles" / "flops_w.json").write_text(json.dumps({"source_hash": h, "fp64_flops_per_launch": 4.5e9}))
+    assert bench.load_traffic("w", 100.0) == 123.0
+    assert bench.load_flops("w") == 4.5e9
+    assert bench.load_traffic("other", 100.0) is None and bench.load_flops("other") is None
+    # any change to a kernel source invalidates both
+    (csrc / "k.hip").write_text("// kernel v2\n")
+    assert bench.source_hash() != h
+    assert bench.load_traffic("w", 100.0) is None
+    assert bench.load_flops("w") is None
+
+
+def test_committed_workloads_are_known():
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    for f in os.listdir(os.path.join(root, "profiles")):
+        if f.endswith(".json"):
+            wl = f.split("_", 1)[1][:-5]
+            assert wl in bench.WORKLOADS, f
