@@ -167,6 +167,18 @@ def test_tiny_and_degenerate_grids(sme, case):
     assert abs(t_gpu - t_orc) <= 1e-12 * t_orc
 
 
+@pytest.mark.parametrize("case", [((1, 1), "wall", 8), ((1, 6), "periodic", 7), ((63, 2), "extrap", 6),
+                                  ((62, 3), "wall", 5), ((2, 63), "periodic", 8)])
+def test_tiny_grids_high_levels(sme, case):
+    """Tiny and wave-edge grids at levels 5..8 (the largest row-staging buffers)."""
+    shape, bc, level = case
+    p = tiny_problem("2d", shape, bc, level=level, seed=level)
+    q_gpu, q_orc, t_gpu, t_orc = run_both(sme, p, 30)
+    scale = np.maximum(np.abs(q_orc).max(axis=1), np.abs(p["q"]).max(axis=1))
+    assert np.max(np.abs(q_gpu - q_orc).max(axis=1) / scale) <= 1e-10
+    assert abs(t_gpu - t_orc) <= 1e-12 * t_orc
+
+
 @pytest.mark.parametrize("ntri", [1, 2])
 def test_one_and_two_triangles(sme, ntri):
     vert = np.array([[0.0, 0.0], [1.0, 0.0], [1.0, 1.0], [0.0, 1.0]])
