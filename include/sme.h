@@ -130,7 +130,13 @@ int sme_step(sme_ctx *ctx, double dt, double *dt_used);
  * no-ops (a copy of the state each).  If t_out / steps_done are not NULL the stream is synchronised
  * and the simulated time since sme_set_state and the number of steps that
  * advanced the state are returned; SME_ENONPHYS is returned if a step produced
- * h <= 0 or a non-finite value (the state is then not usable). */
+ * h <= 0 or a non-finite value (the state is then not usable).
+ * A 1D grid of at most 40 x 62 cells whose state fits in one workgroup's LDS,
+ * with no closure attached, is instead advanced by one workgroup that keeps
+ * the state in LDS and takes up to 2048 steps per launch (its own step loop
+ * stops at t_end; the clock is checked between launches).  The result is
+ * bitwise the same as single sme_step calls.  The environment variable
+ * SME_NO_LDS_RUN selects the graph path for such grids too. */
 int sme_run(sme_ctx *ctx, int64_t n_steps, double t_end, double *t_out, int64_t *steps_done);
 
 /* Simulated time and step count since sme_set_state (synchronises). */

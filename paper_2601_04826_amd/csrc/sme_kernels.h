@@ -115,6 +115,10 @@ int batch_waves_per_simd();  // resident waves per SIMD of the ensemble kernel
 
 // host-side launchers; level is 0..8
 hipError_t launch_step_1d(int level, const StepArgs &a, hipStream_t s);
+// nsteps steps of a 1D grid by one workgroup with the state in LDS (no closure);
+// the final state goes to dst; run_1d_lds_bytes is its dynamic LDS size
+size_t run_1d_lds_bytes(int level, int nx);
+hipError_t launch_run_1d_lds(int level, const StepArgs &a, int nsteps, double *dst, hipStream_t s);
 hipError_t launch_step_2d(int level, const StepArgs &a, hipStream_t s);
 int step_2d_waves_per_simd(int level);  // resident waves per SIMD of the structured step kernel
 hipError_t launch_step_tri(int level, const StepArgs &a, hipStream_t s);

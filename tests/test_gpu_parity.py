@@ -179,6 +179,59 @@ def test_tiny_grids_high_levels(sme, case):
     assert abs(t_gpu - t_orc) <= 1e-12 * t_orc
 
 
+@pytest.mark.parametrize("case", [(0, 1, "periodic"), (1, 1000, "extrap"), (1, 63, "wall"), (2, 500, "periodic"),
+                                  (3, 62, "wall"), (5, 200, "extrap"), (8, 300, "periodic")])
+def test_multi_step_1d_equals_single_steps(sme, case):
+    """sme_run on a small 1D grid (one workgroup, state in LDS, up to 2048
+    steps per launch) against the same number of single step launches of the
+    per-step kernel: bitwise equal state, clock and step count."""
+    level, n, bc = case
+    p = tiny_problem("1d", n, bc, level=level, seed=20 + level)
+    steps = 2500  # two launches of the multi-step kernel
+    a = sme.Solver(p)
+    a.set_state(p["q"])
+    t1, n1 = a.run(steps)
+    q1 = a.get_state()
+    a.close()
+    b = sme.Solver(p)
+    b.set_state(p["q"])
+    for _ in range(steps):
+        b.step(0.0)
+    t2, n2 = b.time()
+    q2 = b.get_state()
+    b.close()
+    assert n1 == n2 == steps
+    assert t1 == t2
+    assert np.array_equal(q1, q2)
+
+
+def test_multi_step_1d_end_time_and_failure(sme, monkeypatch):
+    """With an end time the multi-step kernel stops on it exactly as the graph
+    path does; a non-physical state is reported through it too."""
+    p = tiny_problem("1d", 700, "wall", level=2, seed=31)
+    out = []
+    for env in (None, "1"):
+        if env:
+            monkeypatch.setenv("SME_NO_LDS_RUN", env)
+        s = sme.Solver(p)
+        s.set_state(p["q"])
+        t, k = s.run(10 ** 6, t_end=0.37)
+        out.append((t, k, s.get_state()))
+        s.close()
+    monkeypatch.delenv("SME_NO_LDS_RUN")
+    assert out[0][0] == out[1][0] and abs(out[0][0] - 0.37) <= 1e-15
+    assert out[0][1] == out[1][1]
+    assert np.array_equal(out[0][2], out[1][2])
+    q = p["q"].copy()
+    q[0, 350] = -1.0
+    s = sme.Solver(p)
+    s.set_state(q)
+    with pytest.raises(sme.SmeError) as e:
+        s.run(5)
+    assert e.value.code == sme.SME_ENONPHYS
+    s.close()
+
+
 @pytest.mark.parametrize("ntri", [1, 2])
 def test_one_and_two_triangles(sme, ntri):
     vert = np.array([[0.0, 0.0], [1.0, 0.0], [1.0, 1.0], [0.0, 1.0]])
