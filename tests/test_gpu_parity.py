@@ -209,19 +209,21 @@ def test_multi_step_1d_end_time_and_failure(sme, monkeypatch):
     """With an end time the multi-step kernel stops on it exactly as the graph
     path does; a non-physical state is reported through it too."""
     p = tiny_problem("1d", 700, "wall", level=2, seed=31)
-    out = []
-    for env in (None, "1"):
-        if env:
-            monkeypatch.setenv("SME_NO_LDS_RUN", env)
-        s = sme.Solver(p)
-        s.set_state(p["q"])
-        t, k = s.run(10 ** 6, t_end=0.37)
-        out.append((t, k, s.get_state()))
-        s.close()
-    monkeypatch.delenv("SME_NO_LDS_RUN")
-    assert out[0][0] == out[1][0] and abs(out[0][0] - 0.37) <= 1e-15
-    assert out[0][1] == out[1][1]
-    assert np.array_equal(out[0][2], out[1][2])
+    for t_end in (0.37, 6.0):  # within one launch of the multi-step kernel, and across several
+        out = []
+        for env in (None, "1"):
+            if env:
+                monkeypatch.setenv("SME_NO_LDS_RUN", env)
+            s = sme.Solver(p)
+            s.set_state(p["q"])
+            t, k = s.run(10 ** 6, t_end=t_end)
+            out.append((t, k, s.get_state()))
+            s.close()
+        monkeypatch.delenv("SME_NO_LDS_RUN")
+        print("end time", t_end, "steps", out[0][1], flush=True)
+        assert out[0][0] == out[1][0] and abs(out[0][0] - t_end) <= 1e-14 * t_end
+        assert out[0][1] == out[1][1]
+        assert np.array_equal(out[0][2], out[1][2])
     q = p["q"].copy()
     q[0, 350] = -1.0
     s = sme.Solver(p)
