@@ -131,8 +131,9 @@ int sme_step(sme_ctx *ctx, double dt, double *dt_used);
  * and the simulated time since sme_set_state and the number of steps that
  * advanced the state are returned; SME_ENONPHYS is returned if a step produced
  * h <= 0 or a non-finite value (the state is then not usable).
- * A 1D grid of at most 40 x 62 cells whose state fits in one workgroup's LDS,
- * with no closure attached, is instead advanced by one workgroup that keeps
+ * A small 1D grid (at most 40 x 62 cells at levels 0-1, down to 8 x 62 at
+ * level 8) whose state fits in one workgroup's LDS, with no closure attached,
+ * is instead advanced by one workgroup that keeps
  * the state in LDS and takes up to 2048 steps per launch (its own step loop
  * stops at t_end; the clock is checked between launches).  The result is
  * bitwise the same as single sme_step calls.  The environment variable

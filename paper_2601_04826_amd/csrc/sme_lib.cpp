@@ -25,11 +25,14 @@ namespace {
 
 constexpr int kGraphSteps = 6;  // lcm of the ping-pong period (2) and the slot period (3)
 constexpr int kLdsRunSteps = 2048;  // steps per launch of the multi-step kernel of small 1D grids
-// The multi-step kernel runs on one compute unit: past about 40 windows of 62
-// cells (2.5 per wave) the per-step kernel, spread over the device, is faster
-// (measured: level 1, 2000 cells 4.3 against 5.1 us per step; 2900 cells 5.5
-// against 5.1).
-constexpr int kLdsRunMaxWindows = 40;
+// The multi-step kernel runs on one compute unit, so past some number of
+// 62-cell windows the per-step kernel, spread over the device, is faster; the
+// arithmetic per window grows with the level.  Largest window counts per
+// level, from measurements (us per step, multi-step against graphs): level 1,
+// 2000 cells 4.3 / 5.1, 2900 cells 5.5 / 5.1; level 2, 1800 cells 4.8 / 5.3;
+// level 4, 1200 cells 4.7 / 5.4; level 8, 390 cells 5.2 / 6.9, 900 cells
+// 8.5 / 7.4; levels in between interpolated.
+constexpr int kLdsRunMaxWindows[9] = {40, 40, 32, 26, 20, 16, 12, 10, 8};
 
 struct GraphEntry {
     int cur, slot;
@@ -673,7 +676,8 @@ int sme_run(sme_ctx *c, int64_t n_steps, double t_end, double *t_out, int64_t *s
     // state in LDS, up to kLdsRunSteps per launch (checking the clock between
     // launches when there is an end time)
     if (c->kind == SME_MESH_1D && !c->closure && getenv("SME_NO_LDS_RUN") == nullptr &&
-        (c->nx + 61) / 62 <= kLdsRunMaxWindows && run_1d_lds_bytes(c->level, (int)c->nx) + 1024 <= c->lds_optin) {
+        (c->nx + 61) / 62 <= kLdsRunMaxWindows[c->level] &&
+        run_1d_lds_bytes(c->level, (int)c->nx) + 1024 <= c->lds_optin) {
         while (left > 0) {
             const int k = (int)std::min<int64_t>(left, kLdsRunSteps);
             StepArgs a = make_args(c);

@@ -180,7 +180,10 @@ def test_tiny_grids_high_levels(sme, case):
 
 
 @pytest.mark.parametrize("case", [(0, 1, "periodic"), (1, 1000, "extrap"), (1, 63, "wall"), (2, 500, "periodic"),
-                                  (3, 62, "wall"), (5, 200, "extrap"), (8, 300, "periodic")])
+                                  (3, 62, "wall"), (5, 200, "extrap"), (8, 300, "periodic"),
+                                  # near the limits (more than 64 KB of LDS): level 8, 8 windows and 82 KB;
+                                  # level 1, 40 windows and 139 KB
+                                  (8, 490, "wall"), (1, 2480, "periodic")])
 def test_multi_step_1d_equals_single_steps(sme, case):
     """sme_run on a small 1D grid (one workgroup, state in LDS, up to 2048
     steps per launch) against the same number of single step launches of the
