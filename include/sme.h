@@ -14,17 +14,25 @@
  * eigenvalue bound over the state for the adaptive time step.
  *
  * Numbers and layout
- *   FP64 throughout.  State Q is structure-of-arrays, Q[f * ncells + i], in the
- *   caller's cell order:
+ *   FP64 throughout.  State Q is structure-of-arrays.  The calls that copy a
+ *   state in or out (sme_set_state, sme_get_state) use Q[f * ncells + i] in the
+ *   caller's cell order; the two device buffers a context is bound to use
+ *   Q[f * field_stride + i] in the library's internal cell order (the caller's
+ *   order on 1D and structured meshes):
  *     1D       nfields = N + 2   : (h, q_0 .. q_N),          q_k = h alpha_k
  *     2D       nfields = 2N + 3  : (h, qx_0..qx_N, qy_0..qy_N), qx_k = h alpha_k, qy_k = h beta_k
  *   Bathymetry b[i] is static.  Units: SI, kinematic (rho = 1).
  *
  * Ownership
- *   The context owns its device buffers (state ping-pong, bathymetry, mesh
- *   geometry, time-step slots); they are allocated in sme_init and freed in
- *   sme_destroy.  Pointers passed in are only read during the call; host or
- *   device memory as the on_device flag says.  All device work is queued on the
+ *   The caller owns the two device buffers of the state (the ping-pong pair
+ *   of the explicit step, as in the solver's initialisation, Sec. 2.1.2, which
+ *   hands out the state arrays); sme_init binds them to the context and they
+ *   must outlive it.  Each step reads one and writes the other; sme_current
+ *   says which one holds the state.  The context owns the rest: bathymetry in
+ *   the internal order, mesh geometry, Gauss points and the time-step slots
+ *   (sme_workspace_size bytes, allocated in sme_init, freed in sme_destroy).
+ *   Other pointers passed in are only read during the call; host or device
+ *   memory as the on_device flag says.  All device work is queued on the
  *   HIP stream given to sme_init; a call returns once its work is queued unless
  *   it returns a host value (sme_eigmax, sme_run with t_out/steps_done,
  *   sme_step with dt_used, sme_get_state into host memory), which synchronises
@@ -38,6 +46,7 @@
 #ifndef SME_H
 #define SME_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -94,21 +103,41 @@ typedef struct {
     const int32_t *tri;
 } sme_mesh;
 
-/* Number of fields and cells a (level, mesh) pair needs, without a context. */
-int sme_layout(int level, const sme_mesh *mesh, int *nfields, int64_t *ncells);
+/* Number of fields and cells a (level, mesh) pair needs, and the field stride
+ * (ncells rounded up to a multiple of 256) of the state buffers sme_init
+ * binds; no context and no device work.  Any output pointer may be NULL. */
+int sme_layout(int level, const sme_mesh *mesh, int *nfields, int64_t *ncells, int64_t *field_stride);
 
-/* Create a solver for the SME of the given level (0..8) on the mesh.
+/* Bytes of device memory sme_init allocates for a (level, mesh) pair besides
+ * the caller's state buffers: bathymetry, Gauss points, time-step slots and,
+ * on triangles, neighbours, normals and the two cell permutations.  Attaching
+ * a learned closure adds its network and rates buffers. */
+int sme_workspace_size(int level, const sme_mesh *mesh, size_t *bytes);
+
+/* Create a solver for the SME of the given level (0..8) on the mesh
+ * (the solver initialisation of Sec. 2.1.2: model, mesh and settings in, state
+ * arrays bound).
+ *   q_dev   two distinct caller-owned device buffers of the current device,
+ *           256-byte aligned, each nfields * field_stride doubles (sme_layout);
+ *           they stay owned by the caller and must outlive the context.  The
+ *           library writes them in every step, and on triangles it also uses
+ *           the one not holding the state as scratch in sme_set_state and
+ *           sme_get_state.  SME_EINVAL if a pointer is NULL, not device memory
+ *           of this device, misaligned or (as far as the runtime can tell)
+ *           too short.
  *   b       bathymetry [ncells] in caller cell order (NULL = flat), host or
- *           device memory (b_on_device).
- *   stream  hipStream_t to queue all work on (NULL = the null stream).
- * The state starts at zero depth: call sme_set_state before stepping. */
+ *           device memory (b_on_device); copied.
+ *   stream  hipStream_t to queue all work on (NULL = a stream of the context).
+ * There is no state until sme_set_state. */
 int sme_init(sme_ctx **out, int level, const sme_mesh *mesh, const sme_params *params,
-             const double *b, int b_on_device, void *stream);
+             double *const q_dev[2], const double *b, int b_on_device, void *stream);
 
 /* Load / read the state Q [nfields][ncells] (caller cell order; host memory,
  * or device memory if on_device).  sme_set_state also evaluates the eigenvalue
  * bound of the new state for the next CFL step and clears the time and step
- * counters. */
+ * counters.  On 1D and structured meshes q may also be one of the two bound
+ * buffers (on_device = 1), filled by the caller with field stride
+ * field_stride: that buffer then holds the state and nothing is copied. */
 int sme_set_state(sme_ctx *ctx, const double *q, int on_device);
 int sme_get_state(sme_ctx *ctx, double *q, int on_device);
 
@@ -143,14 +172,18 @@ int sme_run(sme_ctx *ctx, int64_t n_steps, double t_end, double *t_out, int64_t 
 /* Simulated time and step count since sme_set_state (synchronises). */
 int sme_time(sme_ctx *ctx, double *t, int64_t *steps);
 
+/* Which of the two bound buffers (0 or 1, the index into q_dev of sme_init)
+ * holds the current state; it alternates with every step. */
+int sme_current(const sme_ctx *ctx);
+
 int sme_nfields(const sme_ctx *ctx);
 int64_t sme_ncells(const sme_ctx *ctx);
 int sme_level(const sme_ctx *ctx);
 
-/* Device pointer of the current state, in the library's internal cell order
- * (identity for 1D and structured meshes, a bandwidth-reducing permutation for
- * triangles); field f starts at element f * sme_field_stride(ctx) (ncells
- * rounded up to a multiple of 256).  Valid until the next step. */
+/* The bound buffer holding the current state (q_dev[sme_current(ctx)]), in
+ * the library's internal cell order (identity for 1D and structured meshes,
+ * a bandwidth-reducing permutation for triangles); field f starts at element
+ * f * sme_field_stride(ctx) (ncells rounded up to a multiple of 256). */
 const double *sme_state_device(const sme_ctx *ctx);
 int64_t sme_field_stride(const sme_ctx *ctx);
 
@@ -202,6 +235,9 @@ void sme_batch_destroy(sme_batch *bt);
 typedef struct sme_mlp sme_mlp;
 
 int sme_mlp_create(sme_mlp **out, void *stream);
+/* Glorot-uniform initial weights, U(-a, a) with a = sqrt(6 / (fan_in +
+ * fan_out)) drawn from a splitmix64 stream of `seed`, zero biases; resets Adam. */
+int sme_mlp_init(sme_mlp *m, uint64_t seed);
 int sme_mlp_set_params(sme_mlp *m, const float *params, int on_device);
 int sme_mlp_get_params(sme_mlp *m, float *params, int on_device);
 /* Normalisation (mu, sigma: 9 each), output scale (2) and the training box of
@@ -258,6 +294,33 @@ int sme_closure_attach(sme_ctx *ctx, const sme_mlp *m);
 int sme_closure_attach_ex(sme_ctx *ctx, const sme_mlp *m, int precision);
 /* Cell-steps whose features left the training box since sme_set_state. */
 int sme_closure_out_of_range(sme_ctx *ctx, int64_t *cells);
+
+/* Train the network on n raw samples (device arrays feat [n][9], targ [n][2],
+ * FP32): fit the scaling and the training box (sme_mlp_fit_scaling with
+ * `margin`), reset Adam, then `epochs` passes over a seeded permutation of the
+ * samples (splitmix64 stream of `seed`, Fisher-Yates) in max(1, n / batch)
+ * batches of `batch` rows, one Adam step each (sme_mlp_train_step), with the
+ * learning rate decaying geometrically from lr at the first step to lr_end at
+ * the last.  loss_hist (host, `epochs` floats, NULL = none) receives the loss
+ * of the last batch of every epoch.  Synchronises the network's stream. */
+int sme_closure_train(sme_mlp *m, const float *feat, const float *targ, int64_t n, int epochs, int64_t batch,
+                      float lr, float lr_end, uint64_t seed, double margin, float *loss_hist);
+
+/* Level 1 + closure with a fallback.  c1 is a level-1 context with a network
+ * attached and a state loaded, c8 a context of a higher level (normally 8) on
+ * the same grid.  Advances c1 towards t_end (simulated time since its
+ * sme_set_state) in chunks of `chunk` CFL steps, at most max_steps in all; the
+ * state at the start of each chunk is kept on the device.  If more than
+ * max_out_of_range * ncells * (steps of the chunk) cell-steps of a chunk left
+ * the training box, the network is not trusted there: the chunk's starting
+ * state is lifted into c8 (h, q_0, q_1 of each direction copied, higher
+ * moments zero) and c8 runs from it to t_end instead.  Outputs (any may be
+ * NULL): t_out the simulated time reached, steps_done the steps taken
+ * (level-1 steps before the fallback plus c8's), fallback_at the time of the
+ * lifted state, or -1 if c1 ran to the end (the final state is then c1's,
+ * else c8's).  Synchronises both streams. */
+int sme_closure_run(sme_ctx *c1, sme_ctx *c8, double t_end, int64_t chunk, int64_t max_steps,
+                    double max_out_of_range, double *t_out, int64_t *steps_done, double *fallback_at);
 
 /* Introspection, host only (no device work): the FP64 basis tensors the kernels
  * are compiled with (Eq. (1), Sec. 3.4): M[n], A[n*n*n], B[n*n*n], K[n*n] with

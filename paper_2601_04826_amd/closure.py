@@ -1,12 +1,13 @@
 """Learned closure: level 1 plus a small network standing in for level 8.
 
-Everything numeric runs in the library's kernels: the level-8 and level-1 SME
-steps that generate the data, the sample extraction (features and a-priori
+Everything numeric runs in the library: the level-8 and level-1 SME steps
+that generate the data, the sample extraction (features and a-priori
 targets), the feature statistics behind the scaling and the training box, the
-FP32 training step (forward, backward, Adam, batches gathered by index) and
-the rates pass before every level-1 step.  This module only orchestrates
-them: torch holds device buffers, a seeded numpy generator draws the sampled
-cells and the batch permutations.
+initialisation and the training loop (forward, backward, Adam, learning-rate
+schedule, seeded batch permutations: sme_closure_train), the rates pass
+before every level-1 step and the chunked run with its level-8 fallback
+(sme_closure_run).  This module only marshals: torch holds device buffers, a
+seeded numpy generator draws the cells sampled from each snapshot.
 
 Target (a-priori closure): for consecutive level-8 states Q8^n, Q8^{n+1} with
 step dt, r = [P(Q8^{n+1}) - Step_L1(P(Q8^n))] / dt on (q_0, q_1), where P keeps
@@ -74,44 +75,20 @@ def generate(seeds, n=4096, steps=2000, every=10, cells_per_snapshot=256, stream
     return feat, targ
 
 
-def init_params(seed=0):
-    """Glorot-uniform weights, zero biases (flat layout W1, b1, W2, b2, W3, b3)."""
-    rng = np.random.default_rng(seed)
-    parts = []
-    for o, i in ((64, N_IN), (64, 64), (N_OUT, 64)):
-        a = np.sqrt(6.0 / (i + o))
-        parts += [rng.uniform(-a, a, size=o * i), np.zeros(o)]
-    return np.concatenate(parts).astype(np.float32)
-
-
 def fit(feat, targ, epochs=20, batch=4096, lr=2e-3, lr_end=1e-4, seed=0, stream=None, log=None, margin=0.1):
-    """Train the network with the library's FP32 kernels (Adam, MSE on
-    normalised targets) on raw samples; the scaling and the training box come
-    from the library's statistics of the same samples.  Returns (MLP, scaling
-    dict, loss history)."""
+    """Train the network with the library (sme_mlp_init, sme_closure_train:
+    scaling and training box from the samples, Adam on normalised targets with
+    a geometric learning-rate decay, seeded batch permutations).  Returns
+    (MLP, scaling dict, loss history)."""
     st = stream or torch.cuda.Stream()
-    rng = np.random.default_rng(seed)
     with torch.cuda.stream(st):
-        mlp = sme.MLP(init_params(seed), stream=st.cuda_stream)
-        sc = mlp.fit_scaling(feat, targ, margin=margin)
-        S = feat.shape[0]
-        nb = max(1, S // batch)
-        total = epochs * nb
-        hist = []
-        step = 0
-        for ep in range(epochs):
-            perm = torch.from_numpy(rng.permutation(S).astype(np.int64)).cuda()
-            for b in range(nb):
-                idx = perm[b * batch:(b + 1) * batch]
-                frac = step / max(1, total - 1)
-                rate = lr * (lr_end / lr) ** frac  # geometric decay
-                want = b == nb - 1
-                loss = mlp.train_step(feat, targ, rate, idx=idx, want_loss=want)
-                step += 1
-            hist.append(loss)
-            if log:
-                log(f"epoch {ep + 1}/{epochs} loss {loss:.5f}")
-        st.synchronize()
+        mlp = sme.MLP(stream=st.cuda_stream)
+        mlp.init(seed)
+        hist = mlp.train(feat, targ, epochs, batch, lr, lr_end, seed, margin=margin)
+        sc = mlp.get_scaling()
+    if log:
+        for ep, loss in enumerate(hist):
+            log(f"epoch {ep + 1}/{epochs} loss {loss:.5f}")
     return mlp, sc, hist
 
 
@@ -122,50 +99,41 @@ def relative_l1(q, q_ref, fields=(0, 1)):
 
 class ClosureSolver:
     """Level 1 + closure on a 1D or structured grid, with the plain level-8
-    solver as fallback once a cell's features leave the training range."""
+    solver as fallback once the features leave the training range
+    (sme_closure_run: the chunk checkpoints and the fallback stay on the device)."""
 
     def __init__(self, problem8, mlp, chunk=50, stream=None, max_out_of_range=1e-3, precision="fp32"):
         self.p8 = problem8
         self.mlp = mlp
         self.chunk = chunk
         self.max_oor = max_out_of_range  # tolerated fraction of out-of-range cell-steps
-        self.stream = stream
         self.s1 = sme.Solver(_project_any(problem8), stream=stream)
         self.s1.attach_closure(mlp, precision=precision)
-        self.s8 = None
+        self.s8 = sme.Solver(problem8, stream=stream)
         self.fell_back_at = None
 
     def set_state(self, q8):
-        self.q8_init = q8
         self.s1.set_state(_project_state(q8, self.p8))
 
-    def run_to(self, t_end, max_steps=10 ** 7):
-        """Advance to t_end; returns the final state lifted to the level-8 layout."""
-        t = 0.0
-        done = 0
-        while t < t_end and done < max_steps:
-            keep = self.s1.get_state()
-            t_keep = t
-            self.s1.set_state(keep)  # fresh clock for the chunk
-            dt_run, n = self.s1.run(self.chunk, t_end=t_end - t)
-            cells = self.p8["ncells"]
-            if self.s1.out_of_range() > self.max_oor * cells * max(1, n):
-                # fall back: restart this chunk with level 8 from the lifted state
-                self.fell_back_at = t_keep
-                self.s8 = sme.Solver(self.p8, stream=self.stream)
-                self.s8.set_state(_lift_state(keep, self.p8))
-                self.s8.run(max_steps, t_end=t_end - t_keep)
-                return self.s8.get_state()
-            t += dt_run
-            done += n
-            if n == 0:
-                break
+    def run_to(self, t_end, max_steps=10 ** 7, lifted=True):
+        """Advance to t_end; returns the final state lifted to the level-8
+        layout (lifted=False: no copy back, see final_solver)."""
+        t, n, fb = sme.closure_run(self.s1, self.s8, t_end, self.chunk, max_steps, self.max_oor)
+        self.fell_back_at = fb
+        self.t, self.steps = t, n
+        if not lifted:
+            return None
+        if fb is not None:
+            return self.s8.get_state()
         return _lift_state(self.s1.get_state(), self.p8)
+
+    def final_solver(self):
+        """The Solver that holds the final state of the last run_to."""
+        return self.s8 if self.fell_back_at is not None else self.s1
 
     def close(self):
         self.s1.close()
-        if self.s8 is not None:
-            self.s8.close()
+        self.s8.close()
 
 
 def _project_any(problem8):

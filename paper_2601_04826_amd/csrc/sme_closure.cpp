@@ -99,6 +99,20 @@ bool fold_fp16(ClosureModel &cm)
     return wmax <= 65504.0;
 }
 
+// splitmix64: a counter-based 64-bit generator (Steele, Lea and Flood, 2014)
+struct SplitMix64 {
+    uint64_t x;
+    uint64_t next()
+    {
+        uint64_t z = (x += 0x9E3779B97F4A7C15ull);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        return z ^ (z >> 31);
+    }
+    double uniform() { return (double)(next() >> 11) * 0x1.0p-53; }  // [0, 1)
+    uint64_t below(uint64_t k) { return (uint64_t)(((unsigned __int128)next() * k) >> 64); }  // [0, k)
+};
+
 MlpScale scale_of(const sme_mlp *m)
 {
     MlpScale sc{};
@@ -318,6 +332,60 @@ int sme_closure_samples(const double *q8, int64_t stride8, const double *q8_next
     hipError_t e = launch_closure_samples(q8, stride8, q8_next, stride8n, q1_step, stride1, ncells, dt, cells, nsamples,
                                           feat, targ, (hipStream_t)stream);
     return e == hipSuccess ? SME_OK : SME_EHIP;
+}
+
+int sme_mlp_init(sme_mlp *m, uint64_t seed)
+{
+    if (!m) return SME_EINVAL;
+    std::vector<float> p(kMlpParams, 0.0f);
+    SplitMix64 g{seed};
+    // Glorot-uniform weights U(-a, a), a = sqrt(6 / (fan_in + fan_out)); zero biases
+    auto fill = [&](int off, int fan_out, int fan_in) {
+        const double a = std::sqrt(6.0 / (fan_in + fan_out));
+        for (int k = 0; k < fan_out * fan_in; ++k) p[off + k] = (float)((2.0 * g.uniform() - 1.0) * a);
+    };
+    fill(kOffW1, kMlpHid, kMlpIn);
+    fill(kOffW2, kMlpHid, kMlpHid);
+    fill(kOffW3, kMlpOut, kMlpHid);
+    int r = sme_mlp_set_params(m, p.data(), 0);
+    return r ? r : sme_mlp_reset_optimizer(m);
+}
+
+int sme_closure_train(sme_mlp *m, const float *feat, const float *targ, int64_t n, int epochs, int64_t batch,
+                      float lr, float lr_end, uint64_t seed, double margin, float *loss_hist)
+{
+    if (!m || !feat || !targ || n < 2 || epochs < 1 || batch < 1 || !(lr > 0) || !(lr_end > 0)) return SME_EINVAL;
+    int r = sme_mlp_fit_scaling(m, feat, targ, n, margin);
+    if (!r) r = sme_mlp_reset_optimizer(m);
+    if (r) return r;
+    const int64_t bs = std::min(batch, n);
+    const int64_t nb = std::max<int64_t>(1, n / bs);
+    const int64_t total = (int64_t)epochs * nb;
+    std::vector<int64_t> perm(n);
+    int64_t *dperm = nullptr;
+    MCHK(m, hipMalloc((void **)&dperm, (size_t)n * sizeof(int64_t)));
+    SplitMix64 g{seed};
+    int64_t step = 0;
+    for (int ep = 0; ep < epochs && !r; ++ep) {
+        for (int64_t i = 0; i < n; ++i) perm[i] = i;
+        for (int64_t i = n - 1; i > 0; --i) std::swap(perm[i], perm[(int64_t)g.below((uint64_t)i + 1)]);
+        hipError_t e = hipMemcpyAsync(dperm, perm.data(), (size_t)n * sizeof(int64_t), hipMemcpyHostToDevice, m->stream);
+        if (e != hipSuccess) {
+            r = mfail(m, SME_EHIP, "permutation upload: %s", hipGetErrorString(e));
+            break;
+        }
+        float loss = 0.0f;
+        for (int64_t b = 0; b < nb && !r; ++b, ++step) {
+            const double frac = (double)step / (double)std::max<int64_t>(1, total - 1);
+            const float rate = (float)(lr * std::pow((double)lr_end / lr, frac));
+            r = sme_mlp_train_step(m, feat, targ, dperm + b * bs, bs, rate, b == nb - 1 ? &loss : nullptr);
+        }
+        if (!r && loss_hist) loss_hist[ep] = loss;
+    }
+    // the host permutation must not change while a copy may still read it
+    (void)hipStreamSynchronize(m->stream);
+    (void)hipFree(dperm);
+    return r;
 }
 
 int sme_closure_attach_ex(sme_ctx *ctx, const sme_mlp *m, int precision)

@@ -4,6 +4,9 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdint>
+
+#include "sme_kernels.h"
 
 namespace sme {
 namespace host {
@@ -55,6 +58,30 @@ inline int device_cus()
     if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
         return prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
     return 256;
+}
+
+// Height of the row band each wave of the structured kernel marches up.
+// Every band costs its rows plus about 1.5 rows of halo work, and waves run in
+// generations of (compute units x 4 SIMDs x waves per SIMD); a short last
+// generation costs a full band time.  Pick the height that minimises
+// generations x (rows + 1.5) for this grid, level and device.
+inline int pick_rows(int level, int64_t nx, int64_t ny, int cus)
+{
+    const int per_simd = step_2d_waves_per_simd(level);
+    const int64_t slots = (int64_t)cus * 4 * per_simd;
+    const int64_t nsx = (nx + 61) / 62;
+    int best = 8;
+    double best_cost = 1e300;
+    for (int rows = 2; rows <= 64; ++rows) {
+        const int64_t waves = nsx * ((ny + rows - 1) / rows);
+        const int64_t gens = (waves + slots - 1) / slots;
+        const double cost = (double)gens * (rows + 1.5);
+        if (cost < best_cost - 1e-9) {
+            best_cost = cost;
+            best = rows;
+        }
+    }
+    return best;
 }
 
 }  // namespace host

@@ -1,9 +1,11 @@
 // sme_lib.cpp -- host side of the SME library: the C ABI declared in include/sme.h.
 //
-// Owns the per-context device memory, prepares mesh geometry (triangle
-// neighbours, normals, a reverse Cuthill-McKee cell order), the Gauss-Legendre
-// points of the path integral, and queues the step kernels, capturing runs of
-// steps in HIP graphs so a long run costs one graph launch per six steps.
+// Binds the caller's two state buffers (ping-pong) to a context, owns the
+// per-context tables (bathymetry in the internal cell order, triangle
+// neighbours, normals and a reverse Cuthill-McKee cell order, the
+// Gauss-Legendre points of the path integral) and the time-step slots, and
+// queues the step kernels, capturing runs of steps in HIP graphs so a long
+// run costs one graph launch per six steps.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -58,7 +60,7 @@ struct sme_ctx {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     int device = 0;
-    // device memory
+    // device memory: the state buffers belong to the caller, the rest to the context
     double *q[2] = {nullptr, nullptr};
     double *b = nullptr;
     int32_t *nbr = nullptr;
@@ -72,6 +74,7 @@ struct sme_ctx {
     unsigned long long *oor = nullptr;  // cells that left the closure's training range
     float *rates = nullptr;             // closure rates of the current state (2 or 4 per cell)
     int closure_mode = 0;               // ClosurePrecision of the attached network
+    double *ckpt = nullptr;             // state at the start of a closure chunk (sme_closure_run)
     double *t_host = nullptr;           // pinned: simulated time after the latest graph with an end time
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};  // completion of the last graphs of a run
     int cus = 256;                      // compute units of the device
@@ -105,6 +108,30 @@ int fail(sme_ctx *c, int code, const char *fmt, ...)
     } while (0)
 
 int nfields_of(int level, int kind) { return kind == SME_MESH_1D ? level + 2 : 2 * level + 3; }
+
+// field stride of a state: ncells rounded up to 256 elements (every field starts 2 KiB aligned)
+int64_t stride_of(int64_t ncells) { return (ncells + 255) / 256 * 256; }
+
+// A caller's state buffer must be device memory of the current device, at
+// least `bytes` long from p, and 256-byte aligned.
+int check_device_buffer(sme_ctx *c, const void *p, size_t bytes)
+{
+    if (((uintptr_t)p & 255u) != 0) return fail(c, SME_EINVAL, "state buffer %p is not 256-byte aligned", p);
+    hipPointerAttribute_t at{};
+    if (hipPointerGetAttributes(&at, p) != hipSuccess || at.type != hipMemoryTypeDevice || at.device != c->device) {
+        (void)hipGetLastError();
+        return fail(c, SME_EINVAL, "state buffer %p is not device memory of device %d", p, c->device);
+    }
+    void *base = nullptr;
+    size_t size = 0;
+    if (hipMemGetAddressRange((hipDeviceptr_t *)&base, &size, (hipDeviceptr_t)p) == hipSuccess && base) {
+        if ((const char *)p + bytes > (const char *)base + size)
+            return fail(c, SME_EINVAL, "state buffer %p holds fewer than %zu bytes", p, bytes);
+    } else {
+        (void)hipGetLastError();
+    }
+    return SME_OK;
+}
 
 int check_mesh(const sme_mesh *m, int level, int *nf, int64_t *nc)
 {
@@ -266,31 +293,6 @@ std::vector<int64_t> rcm_order(const std::vector<int32_t> &nbr, int64_t n)
     return order;
 }
 
-// Height of the row band each wave of the structured kernel marches up.
-// Every band costs its rows plus about 1.5 rows of halo work, and waves run in
-// generations of (compute units x 4 SIMDs x waves per SIMD); a short last
-// generation costs a full band time.  Pick the height that minimises
-// generations x (rows + 1.5) for this grid, level and device.
-int pick_rows(int level, int64_t nx, int64_t ny)
-{
-    const int cus = host::device_cus();
-    const int per_simd = step_2d_waves_per_simd(level);
-    const int64_t slots = (int64_t)cus * 4 * per_simd;
-    const int64_t nsx = (nx + 61) / 62;
-    int best = 8;
-    double best_cost = 1e300;
-    for (int rows = 2; rows <= 64; ++rows) {
-        const int64_t waves = nsx * ((ny + rows - 1) / rows);
-        const int64_t gens = (waves + slots - 1) / slots;
-        const double cost = (double)gens * (rows + 1.5);
-        if (cost < best_cost - 1e-9) {
-            best_cost = cost;
-            best = rows;
-        }
-    }
-    return best;
-}
-
 template <typename T>
 int dalloc(sme_ctx *c, T **p, size_t count)
 {
@@ -430,7 +432,7 @@ void copy_tensors(double *M, double *A, double *B, double *K)
 
 extern "C" {
 
-int sme_layout(int level, const sme_mesh *mesh, int *nfields, int64_t *ncells)
+int sme_layout(int level, const sme_mesh *mesh, int *nfields, int64_t *ncells, int64_t *field_stride)
 {
     int nf = 0;
     int64_t nc = 0;
@@ -438,13 +440,31 @@ int sme_layout(int level, const sme_mesh *mesh, int *nfields, int64_t *ncells)
     if (r != SME_OK) return r;
     if (nfields) *nfields = nf;
     if (ncells) *ncells = nc;
+    if (field_stride) *field_stride = stride_of(nc);
     return SME_OK;
 }
 
-int sme_init(sme_ctx **out, int level, const sme_mesh *mesh, const sme_params *params, const double *b,
-             int b_on_device, void *stream)
+int sme_workspace_size(int level, const sme_mesh *mesh, size_t *bytes)
 {
-    if (!out || !params) return SME_EINVAL;
+    int nf = 0;
+    int64_t nc = 0;
+    int r = check_mesh(mesh, level, &nf, &nc);
+    if (r != SME_OK) return r;
+    if (!bytes) return SME_EINVAL;
+    const size_t st = (size_t)stride_of(nc);
+    size_t n = st * sizeof(double)                 // bathymetry (internal order)
+               + 3 * sizeof(Slot) + sizeof(ErrWord) + 2 * kMaxQuad * sizeof(double);
+    if (mesh->kind == SME_MESH_2D_TRI)
+        n += 3 * st * (sizeof(int32_t) + 3 * sizeof(double))  // neighbours, normals, |e|/|V|
+             + 2 * (size_t)nc * sizeof(int64_t);             // the two permutations
+    *bytes = n;
+    return SME_OK;
+}
+
+int sme_init(sme_ctx **out, int level, const sme_mesh *mesh, const sme_params *params, double *const q_dev[2],
+             const double *b, int b_on_device, void *stream)
+{
+    if (!out || !params || !q_dev || !q_dev[0] || !q_dev[1] || q_dev[0] == q_dev[1]) return SME_EINVAL;
     *out = nullptr;
     int nf;
     int64_t nc;
@@ -459,7 +479,7 @@ int sme_init(sme_ctx **out, int level, const sme_mesh *mesh, const sme_params *p
     c->kind = mesh->kind;
     c->nf = nf;
     c->ncells = nc;
-    c->stride = (nc + 255) / 256 * 256;
+    c->stride = stride_of(nc);
     c->p = *params;
     double qs[kMaxQuad] = {0}, qw[kMaxQuad] = {0};
     host::gauss_legendre01(params->quad_points, qs, qw);
@@ -500,11 +520,13 @@ int sme_init(sme_ctx **out, int level, const sme_mesh *mesh, const sme_params *p
         c->dx = (mesh->x1 - mesh->x0) / mesh->nx;
         c->dy = (mesh->y1 - mesh->y0) / mesh->ny;
         const char *env = getenv("SME_ROWS");
-        c->rows = env ? std::max(1, atoi(env)) : pick_rows(c->level, c->nx, c->ny);
+        c->rows = env ? std::max(1, atoi(env)) : host::pick_rows(c->level, c->nx, c->ny, host::device_cus());
     }
     int rc = SME_OK;
-    rc = rc ? rc : dalloc(c, &c->q[0], (size_t)nf * c->stride);
-    rc = rc ? rc : dalloc(c, &c->q[1], (size_t)nf * c->stride);
+    for (int k = 0; k < 2 && !rc; ++k) {
+        c->q[k] = q_dev[k];
+        rc = check_device_buffer(c, q_dev[k], (size_t)nf * c->stride * sizeof(double));
+    }
     rc = rc ? rc : dalloc(c, &c->b, (size_t)c->stride);
     rc = rc ? rc : dalloc(c, &c->slots, 3);
     rc = rc ? rc : dalloc(c, &c->err, 1);
@@ -570,8 +592,6 @@ int sme_init(sme_ctx **out, int level, const sme_mesh *mesh, const sme_params *p
                                    c->stream);
             }
         }
-        if (e == hipSuccess) e = hipMemsetAsync(c->q[0], 0, (size_t)nf * c->stride * sizeof(double), c->stream);
-        if (e == hipSuccess) e = hipMemsetAsync(c->q[1], 0, (size_t)nf * c->stride * sizeof(double), c->stream);
         if (e == hipSuccess) e = launch_slots_reset(c->slots, c->err, 0, c->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
         if (e != hipSuccess) rc = fail(c, SME_EHIP, "init upload: %s", hipGetErrorString(e));
@@ -593,6 +613,12 @@ int sme_set_state(sme_ctx *c, const double *q, int on_device)
         double *tmp = c->q[1 - c->cur];
         HIPCHK(c, hipMemcpy2DAsync(tmp, c->stride * sizeof(double), q, row, row, c->nf, kind, c->stream));
         HIPCHK(c, launch_permute(tmp, c->stride, c->q[c->cur], c->stride, c->to_internal, c->ncells, c->nf, c->stream));
+    } else if (q == c->q[c->cur] || q == c->q[1 - c->cur]) {
+        // the caller wrote the state into one of its bound buffers in place
+        // (field stride of the context): adopt that buffer
+        if (!on_device) return fail(c, SME_EINVAL, "a bound state buffer is device memory");
+        c->cur = q == c->q[c->cur] ? c->cur : 1 - c->cur;
+        drop_graphs(c);
     } else {
         HIPCHK(c, hipMemcpy2DAsync(c->q[c->cur], c->stride * sizeof(double), q, row, row, c->nf, kind, c->stream));
     }
@@ -751,6 +777,7 @@ int sme_time(sme_ctx *c, double *t, int64_t *steps)
     return SME_OK;
 }
 
+int sme_current(const sme_ctx *c) { return c ? c->cur : SME_EINVAL; }
 int sme_nfields(const sme_ctx *c) { return c ? c->nf : SME_EINVAL; }
 int64_t sme_ncells(const sme_ctx *c) { return c ? c->ncells : SME_EINVAL; }
 int sme_level(const sme_ctx *c) { return c ? c->level : SME_EINVAL; }
@@ -822,6 +849,74 @@ __attribute__((visibility("hidden"))) int sme_internal_oor(sme_ctx *c, int64_t *
 
 __attribute__((visibility("hidden"))) hipStream_t sme_internal_stream(sme_ctx *c) { return c ? c->stream : nullptr; }
 
+int sme_closure_run(sme_ctx *c1, sme_ctx *c8, double t_end, int64_t chunk, int64_t max_steps,
+                    double max_out_of_range, double *t_out, int64_t *steps_done, double *fallback_at)
+{
+    if (!c1 || !c8 || !(t_end > 0) || chunk < 1 || max_steps < 1 || !(max_out_of_range >= 0)) return SME_EINVAL;
+    if (!c1->closure) return fail(c1, SME_EINVAL, "no closure attached");
+    if (!c1->has_state) return fail(c1, SME_EINVAL, "no state loaded");
+    if (c8->kind != c1->kind || c8->nx != c1->nx || c8->ny != c1->ny || c8->level < 2)
+        return fail(c1, SME_EINVAL, "the fallback context must be a higher level on the same grid");
+    if (!c1->ckpt && dalloc(c1, &c1->ckpt, (size_t)c1->nf * c1->stride)) return SME_ENOMEM;
+    const size_t bytes = (size_t)c1->nf * c1->stride * sizeof(double);
+    if (fallback_at) *fallback_at = -1.0;
+    Slot s;
+    int r = read_slot(c1, &s, nullptr);
+    if (r) return r;
+    double t = s.t;
+    int64_t steps = s.step;
+    int64_t oor = 0;
+    r = sme_internal_oor(c1, &oor);
+    if (r) return r;
+    const int64_t step0 = steps;
+    while (t < t_end && steps - step0 < max_steps) {
+        // checkpoint of the chunk's start (device to device)
+        HIPCHK(c1, hipMemcpyAsync(c1->ckpt, c1->q[c1->cur], bytes, hipMemcpyDeviceToDevice, c1->stream));
+        double t1;
+        int64_t n1;
+        r = sme_run(c1, std::min(chunk, max_steps - (steps - step0)), t_end, &t1, &n1);
+        if (r) return r;
+        int64_t oor1 = 0;
+        r = sme_internal_oor(c1, &oor1);
+        if (r) return r;
+        const int64_t n = n1 - steps;
+        if ((double)(oor1 - oor) > max_out_of_range * (double)c1->ncells * (double)std::max<int64_t>(1, n)) {
+            // the network left its training range in this chunk: redo it, and
+            // the rest of the run, with the fallback level from the chunk's
+            // start, lifted (the higher moments start at zero)
+            if (fallback_at) *fallback_at = t;
+            double *dst = c8->q[c8->cur];
+            const int nb = c1->kind == SME_MESH_1D ? 1 : 2;  // moment blocks
+            const int n1m = 2, n8m = c8->level + 1;             // moments per block
+            HIPCHK(c1, hipStreamSynchronize(c1->stream));
+            HIPCHK(c8, hipMemsetAsync(dst, 0, (size_t)c8->nf * c8->stride * sizeof(double), c8->stream));
+            HIPCHK(c8, hipMemcpyAsync(dst, c1->ckpt, (size_t)c1->stride * sizeof(double), hipMemcpyDeviceToDevice,
+                                      c8->stream));
+            for (int blk = 0; blk < nb; ++blk)
+                HIPCHK(c8, hipMemcpyAsync(dst + (1 + (int64_t)blk * n8m) * c8->stride,
+                                          c1->ckpt + (1 + (int64_t)blk * n1m) * c1->stride,
+                                          (size_t)n1m * c1->stride * sizeof(double), hipMemcpyDeviceToDevice,
+                                          c8->stream));
+            r = sme_set_state(c8, dst, 1);
+            if (r) return r;
+            double t8;
+            int64_t n8;
+            r = sme_run(c8, max_steps - (steps - step0), t_end - t, &t8, &n8);
+            if (r) return r;
+            if (t_out) *t_out = t + t8;
+            if (steps_done) *steps_done = steps + n8;
+            return SME_OK;
+        }
+        oor = oor1;
+        steps = n1;
+        if (n == 0) break;
+        t = t1;
+    }
+    if (t_out) *t_out = t;
+    if (steps_done) *steps_done = steps;
+    return SME_OK;
+}
+
 const char *sme_strerror(int code)
 {
     switch (code) {
@@ -842,8 +937,6 @@ void sme_destroy(sme_ctx *c)
     if (!c) return;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     drop_graphs(c);
-    (void)hipFree(c->q[0]);
-    (void)hipFree(c->q[1]);
     (void)hipFree(c->b);
     (void)hipFree(c->nbr);
     (void)hipFree(c->fnx);
@@ -857,6 +950,7 @@ void sme_destroy(sme_ctx *c)
     (void)hipFree(c->closure);
     (void)hipFree(c->oor);
     (void)hipFree(c->rates);
+    (void)hipFree(c->ckpt);
     if (c->t_host) (void)hipHostFree(c->t_host);
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);

@@ -26,17 +26,18 @@ MAX_LEVEL = 8
 CLOSURE_PRECISIONS = {"fp32": 0, "fp16": 1}  # SME_CLOSURE_FP32, SME_CLOSURE_FP16_MFMA
 
 EXPORTS = [
-    "sme_layout", "sme_init", "sme_set_state", "sme_get_state", "sme_eigmax", "sme_step",
-    "sme_run", "sme_time", "sme_nfields", "sme_ncells", "sme_level", "sme_state_device",
+    "sme_layout", "sme_workspace_size", "sme_init", "sme_set_state", "sme_get_state", "sme_eigmax", "sme_step",
+    "sme_run", "sme_time", "sme_current", "sme_nfields", "sme_ncells", "sme_level", "sme_state_device",
     "sme_field_stride",
     "sme_basis_tensors", "sme_strerror", "sme_last_error", "sme_destroy",
     "sme_batch_init", "sme_batch_set_state", "sme_batch_get_state", "sme_batch_run", "sme_batch_time",
     "sme_batch_cells", "sme_batch_rows", "sme_batch_set_rows", "sme_batch_autotune",
     "sme_batch_last_error", "sme_batch_destroy",
-    "sme_mlp_create", "sme_mlp_set_params", "sme_mlp_get_params", "sme_mlp_set_scaling", "sme_mlp_fit_scaling",
+    "sme_mlp_create", "sme_mlp_init", "sme_mlp_set_params", "sme_mlp_get_params", "sme_mlp_set_scaling", "sme_mlp_fit_scaling",
     "sme_mlp_get_scaling", "sme_mlp_forward",
     "sme_mlp_loss_grad", "sme_mlp_train_step", "sme_mlp_reset_optimizer", "sme_mlp_last_error", "sme_mlp_destroy",
     "sme_closure_samples", "sme_closure_attach", "sme_closure_attach_ex", "sme_closure_out_of_range",
+    "sme_closure_train", "sme_closure_run",
 ]
 
 
@@ -66,14 +67,16 @@ def _load():
     vp, i64, d, i = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int
     P = ctypes.POINTER
     sig = {
-        "sme_layout": (i, [i, vp, P(i), P(i64)]),
-        "sme_init": (i, [P(vp), i, vp, vp, vp, i, vp]),
+        "sme_layout": (i, [i, vp, P(i), P(i64), P(i64)]),
+        "sme_workspace_size": (i, [i, vp, P(ctypes.c_size_t)]),
+        "sme_init": (i, [P(vp), i, vp, vp, P(vp), vp, i, vp]),
         "sme_set_state": (i, [vp, vp, i]),
         "sme_get_state": (i, [vp, vp, i]),
         "sme_eigmax": (i, [vp, P(d), P(d)]),
         "sme_step": (i, [vp, d, P(d)]),
         "sme_run": (i, [vp, i64, d, P(d), P(i64)]),
         "sme_time": (i, [vp, P(d), P(i64)]),
+        "sme_current": (i, [vp]),
         "sme_nfields": (i, [vp]),
         "sme_ncells": (i64, [vp]),
         "sme_level": (i, [vp]),
@@ -95,6 +98,7 @@ def _load():
         "sme_batch_last_error": (ctypes.c_char_p, [vp]),
         "sme_batch_destroy": (None, [vp]),
         "sme_mlp_create": (i, [P(vp), vp]),
+        "sme_mlp_init": (i, [vp, ctypes.c_uint64]),
         "sme_mlp_set_params": (i, [vp, vp, i]),
         "sme_mlp_get_params": (i, [vp, vp, i]),
         "sme_mlp_set_scaling": (i, [vp, vp, vp, vp, vp, vp]),
@@ -110,6 +114,8 @@ def _load():
         "sme_closure_attach": (i, [vp, vp]),
         "sme_closure_attach_ex": (i, [vp, vp, i]),
         "sme_closure_out_of_range": (i, [vp, P(i64)]),
+        "sme_closure_train": (i, [vp, vp, vp, i64, i, i64, ctypes.c_float, ctypes.c_float, ctypes.c_uint64, d, vp]),
+        "sme_closure_run": (i, [vp, vp, d, i64, i64, d, P(d), P(i64), P(d)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -172,12 +178,30 @@ def make_mesh(problem):
 
 
 def sme_layout(level, mesh):
-    nf, nc = ctypes.c_int(), ctypes.c_int64()
-    _check(_lib.sme_layout(level, ctypes.byref(mesh), ctypes.byref(nf), ctypes.byref(nc)))
-    return nf.value, nc.value
+    """(nfields, ncells, field_stride) of a level on a mesh."""
+    nf, nc, st = ctypes.c_int(), ctypes.c_int64(), ctypes.c_int64()
+    _check(_lib.sme_layout(level, ctypes.byref(mesh), ctypes.byref(nf), ctypes.byref(nc), ctypes.byref(st)))
+    return nf.value, nc.value, st.value
 
 
-def sme_init(level, mesh, params, b=None, stream=None):
+def sme_workspace_size(level, mesh):
+    n = ctypes.c_size_t()
+    _check(_lib.sme_workspace_size(level, ctypes.byref(mesh), ctypes.byref(n)))
+    return n.value
+
+
+def state_buffers(level, mesh, device=None):
+    """Two caller-owned device buffers [nfields, field_stride] (float64) for sme_init."""
+    nf, _, st = sme_layout(level, mesh)
+    dev = device if device is not None else torch.device("cuda", torch.cuda.current_device())
+    return [torch.empty((nf, st), dtype=torch.float64, device=dev) for _ in range(2)]
+
+
+def sme_init(level, mesh, params, q_dev, b=None, stream=None):
+    """Context bound to the two device buffers q_dev (torch CUDA tensors)."""
+    if len(q_dev) != 2 or not all(isinstance(x, torch.Tensor) and x.is_cuda for x in q_dev):
+        raise TypeError("q_dev must be two torch CUDA tensors")
+    qp = (ctypes.c_void_p * 2)(q_dev[0].data_ptr(), q_dev[1].data_ptr())
     ctx = ctypes.c_void_p()
     if b is not None:
         if not isinstance(b, torch.Tensor):
@@ -187,8 +211,9 @@ def sme_init(level, mesh, params, b=None, stream=None):
         bp, bdev = None, False
     if stream is None and torch.cuda.is_available():
         stream = torch.cuda.current_stream().cuda_stream
-    _check(_lib.sme_init(ctypes.byref(ctx), level, ctypes.byref(mesh), ctypes.byref(params), bp,
-                         int(bdev), ctypes.c_void_p(stream or 0)))
+    code = _lib.sme_init(ctypes.byref(ctx), level, ctypes.byref(mesh), ctypes.byref(params), qp, bp,
+                         int(bdev), ctypes.c_void_p(stream or 0))
+    _check(code)
     return ctx
 
 
@@ -260,7 +285,10 @@ class Solver:
         self.level = problem["level"]
         self.params = make_params(**p)
         self.mesh, keep = make_mesh(problem)
-        self.ctx = sme_init(self.level, self.mesh, self.params, problem.get("b"), stream)
+        self.ctx = None
+        # the state buffers belong to this object (torch memory), bound to the context
+        self.q_dev = state_buffers(self.level, self.mesh)
+        self.ctx = sme_init(self.level, self.mesh, self.params, self.q_dev, problem.get("b"), stream)
         del keep
         self.nf = _lib.sme_nfields(self.ctx)
         self.ncells = _lib.sme_ncells(self.ctx)
@@ -302,6 +330,10 @@ class Solver:
     def state_device(self):
         """(pointer, field stride) of the current state in the internal order."""
         return _lib.sme_state_device(self.ctx), _lib.sme_field_stride(self.ctx)
+
+    def current(self):
+        """The bound buffer (torch tensor [nfields, field_stride]) holding the state."""
+        return self.q_dev[_lib.sme_current(self.ctx)]
 
     def close(self):
         if self.ctx:
@@ -419,6 +451,20 @@ class MLP:
         if params is not None:
             self.set_params(params)
 
+    def init(self, seed):
+        """Glorot-uniform weights from a seeded stream, zero biases (library call)."""
+        _mcheck(_lib.sme_mlp_init(self.ctx, int(seed)), self.ctx)
+
+    def train(self, feat, targ, epochs, batch, lr, lr_end, seed, margin=0.1):
+        """sme_closure_train on raw samples (CUDA float32 [n, 9], [n, 2]);
+        returns the last-batch loss of every epoch."""
+        hist = np.zeros(epochs, dtype=np.float32)
+        _mcheck(_lib.sme_closure_train(self.ctx, ctypes.c_void_p(feat.data_ptr()), ctypes.c_void_p(targ.data_ptr()),
+                                       feat.shape[0], int(epochs), int(batch), ctypes.c_float(lr),
+                                       ctypes.c_float(lr_end), int(seed), float(margin),
+                                       hist.ctypes.data_as(ctypes.c_void_p)), self.ctx)
+        return [float(x) for x in hist]
+
     def set_params(self, params):
         p = np.ascontiguousarray(params, dtype=np.float32)
         assert p.size == NPARAM
@@ -514,3 +560,11 @@ def closure_samples(q8, q8_next, q1_step, dt, cells, stream=None, out=None):
                                     ctypes.c_void_p(targ.data_ptr()), ctypes.c_void_p(stream or 0))
     _check(code)
     return feat, targ
+
+
+def closure_run(s1, s8, t_end, chunk, max_steps, max_out_of_range):
+    """sme_closure_run on two Solvers; returns (t, steps, fallback_at or None)."""
+    t, n, fb = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
+    _check(_lib.sme_closure_run(s1.ctx, s8.ctx, float(t_end), int(chunk), int(max_steps), float(max_out_of_range),
+                                ctypes.byref(t), ctypes.byref(n), ctypes.byref(fb)), s1.ctx)
+    return t.value, n.value, (fb.value if fb.value >= 0 else None)

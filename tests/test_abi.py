@@ -51,9 +51,9 @@ def test_library_tensors_equal_exact_rationals(sme, level):
 
 def test_layout_and_validation(sme):
     m, _ = sme.make_mesh(dict(kind="2d", nx=10, ny=7, x0=0, x1=1, y0=0, y1=1, bc=("wall",) * 4))
-    assert sme.sme_layout(3, m) == (9, 70)
+    assert sme.sme_layout(3, m) == (9, 70, 256)
     m1, _ = sme.make_mesh(dict(kind="1d", nx=12, x0=0, x1=1, bc=("extrap", "extrap")))
-    assert sme.sme_layout(8, m1) == (10, 12)
+    assert sme.sme_layout(8, m1) == (10, 12, 256)
     with pytest.raises(sme.SmeError) as e:
         sme.sme_layout(9, m)
     assert e.value.code == sme.SME_EINVAL
@@ -62,7 +62,7 @@ def test_layout_and_validation(sme):
         sme.sme_layout(1, bad)
     vert = np.array([[0.0, 0.0], [1.0, 0.0], [0.0, 1.0]])
     t, _ = sme.make_mesh(dict(kind="tri", vert=vert, tri=np.array([[0, 1, 2]], dtype=np.int32)))
-    assert sme.sme_layout(2, t) == (7, 1)
+    assert sme.sme_layout(2, t) == (7, 1, 256)
 
 
 @pytest.mark.parametrize("mesh", [
@@ -78,6 +78,18 @@ def test_layout_rejects_empty_and_invalid_meshes(sme, mesh):
     with pytest.raises(sme.SmeError) as e:
         sme.sme_layout(1, m)
     assert e.value.code == sme.SME_EINVAL
+
+
+def test_workspace_size(sme):
+    m, _ = sme.make_mesh(dict(kind="2d", nx=300, ny=7, x0=0, x1=1, y0=0, y1=1, bc=("wall",) * 4))
+    nf, nc, st = sme.sme_layout(2, m)
+    assert (nf, nc, st) == (7, 2100, 2304)
+    ws = sme.sme_workspace_size(2, m)
+    assert st * 8 <= ws < st * 8 + 16384          # bathymetry plus a few small tables
+    vert = np.array([[0.0, 0.0], [1.0, 0.0], [0.0, 1.0], [1.0, 1.0]])
+    t, _ = sme.make_mesh(dict(kind="tri", vert=vert, tri=np.array([[0, 1, 2], [1, 3, 2]], dtype=np.int32)))
+    wt = sme.sme_workspace_size(3, t)
+    assert wt >= 256 * 8 + 3 * 256 * (4 + 24) + 2 * 2 * 8
 
 
 def test_strerror(sme):

@@ -397,9 +397,8 @@ def test_closure_solver_falls_back_to_level8(env, precision):
 
 
 def test_closure_solver_in_range_runs_level1(env):
-    """A zero network trusted everywhere: no fallback, and chunked runs equal
-    one uninterrupted level-1 run (up to the last step of each chunk, which
-    lands on the end time from a fresh clock)."""
+    """A zero network trusted everywhere: no fallback, and the chunked run
+    (device checkpoints between chunks) is bitwise one uninterrupted level-1 run."""
     torch, sme, closure = env
     p8 = W.smooth_1d(n=256, level=8, seed=1013)
     m = sme.MLP(np.zeros(omlp.NPARAM, dtype=np.float32))
@@ -414,8 +413,8 @@ def test_closure_solver_in_range_runs_level1(env):
     s1.run(10 ** 6, t_end=0.05)
     ref = closure._lift_state(s1.get_state(), p8)
     s1.close()
-    np.testing.assert_allclose(out, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
-    assert np.all(out[3:] == 0.0)
+    assert np.array_equal(out, ref)
+    assert cs.t == pytest.approx(0.05, rel=1e-14)
     m.close()
 
 
