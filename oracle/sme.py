@@ -42,6 +42,7 @@ def lib():
         _lib.oracle_lambda.argtypes = [p, p, d, d]
         _lib.oracle_lambda.restype = d
         _lib.oracle_source.argtypes = [p, p, p]
+        _lib.oracle_friction_step.argtypes = [p, p, d, p]
         _lib.oracle_step_cells.argtypes = [p, p, d, p, i64, p]
         _lib.oracle_predict_cells.argtypes = [p, p, d, p, i64, p]
         _lib.oracle_cfl_dt.argtypes = [p, p, p]
@@ -62,7 +63,7 @@ class _OMesh(ctypes.Structure):
         ("cfl", ctypes.c_double),
         ("nquad", ctypes.c_int), ("qs", ctypes.c_void_p), ("qw", ctypes.c_void_p),
         ("M", ctypes.c_void_p), ("A", ctypes.c_void_p), ("B", ctypes.c_void_p),
-        ("K", ctypes.c_void_p), ("phi0", ctypes.c_void_p),
+        ("K", ctypes.c_void_p), ("phi0", ctypes.c_void_p), ("implicit", ctypes.c_int),
     ]
 
 
@@ -83,7 +84,8 @@ def nfields(level, dim):
 class Oracle:
     """SME oracle bound to one mesh, level and parameter set."""
 
-    def __init__(self, level, mesh, b=None, g=9.81, c_slip=0.0, nu=0.0, cfl=0.45, quad_points=3):
+    def __init__(self, level, mesh, b=None, g=9.81, c_slip=0.0, nu=0.0, cfl=0.45, quad_points=3,
+                 implicit_friction=0):
         self.level = level
         self.mesh = mesh
         self.dim = mesh.dim
@@ -102,12 +104,14 @@ class Oracle:
         bb = np.zeros(mesh.ncells) if b is None else np.ascontiguousarray(b, dtype=np.float64)
         self._keep["b"] = bb
         self.b = bb
-        self.params = dict(g=g, c_slip=c_slip, nu=nu, cfl=cfl, quad_points=quad_points)
+        self.params = dict(g=g, c_slip=c_slip, nu=nu, cfl=cfl, quad_points=quad_points,
+                           implicit_friction=int(implicit_friction))
         k = self._keep
         self._o = _OMesh(level, mesh.dim, mesh.ncells, mesh.maxf,
                          _p(mesh.nbr), _p(mesh.nx), _p(mesh.ny), _p(mesh.flen), _p(mesh.vol),
                          _p(bb), g, c_slip, nu, cfl, quad_points, _p(k["qs"]), _p(k["qw"]),
-                         _p(k["M"]), _p(k["A"]), _p(k["B"]), _p(k["K"]), _p(k["phi0"]))
+                         _p(k["M"]), _p(k["A"]), _p(k["B"]), _p(k["K"]), _p(k["phi0"]),
+                         int(implicit_friction))
         self._lib = lib()
 
     # --- pointwise pieces --------------------------------------------------
@@ -132,6 +136,14 @@ class Oracle:
         q = np.ascontiguousarray(q, dtype=np.float64)
         out = np.zeros(self.nf)
         self._lib.oracle_source(ctypes.byref(self._o), _p(q), _p(out))
+        return out
+
+    def friction_step(self, qstar, dt):
+        """The friction ODE over one step from the predicted state of one cell
+        (explicit or implicit as the oracle was built)."""
+        q = np.ascontiguousarray(qstar, dtype=np.float64)
+        out = np.zeros(self.nf)
+        self._lib.oracle_friction_step(ctypes.byref(self._o), _p(q), float(dt), _p(out))
         return out
 
     # --- whole-mesh operations --------------------------------------------

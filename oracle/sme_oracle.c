@@ -24,6 +24,11 @@
  *     straight path Q_i -> Q_j (Gauss-Legendre in s) is split half/half.
  *   * lam(Q, n) = |a_0| + sqrt(g h + (sum_{j>=1} |a_j|)^2), a_j = normal moment velocity.
  *   * dt = CFL * min_i 2 |V_i| / sum_f |e_f| lam(Q_i, n_f).
+ *   * the friction ODE of the splitting (Eq. (3d)) is integrated by one
+ *     forward-Euler step on the predicted state, or (implicit = 1) by one
+ *     backward-Euler step: S is linear in the momenta for the fixed depth of
+ *     the source step, so Q^{n+1} solves (I - dt L) q = q* per moment block,
+ *     L the (N+1)x(N+1) matrix of S; Gaussian elimination with partial pivoting.
  *
  * State layout: SoA, Q[f * ncells + i].  1D fields (h, q_0..q_N);
  * 2D fields (h, qx_0..qx_N, qy_0..qy_N) with qx_k = h alpha_k, qy_k = h beta_k.
@@ -59,6 +64,7 @@ typedef struct {
     const double *B;          /* [n*n*n] */
     const double *K;          /* [n*n] */
     const double *phi0;       /* [n] */
+    int implicit;             /* 0: explicit friction step, 1: implicit (backward Euler) */
 } omesh;
 
 static int nfields(const omesh *o) { return o->dim == 1 ? o->level + 2 : 2 * o->level + 3; }
@@ -171,6 +177,75 @@ void oracle_source(const omesh *o, const double *q, double *out)
     }
 }
 
+/* Matrix L of the friction source of one moment block at depth h:
+ * S_k(q) = sum_j L_kj q_j with q_j = h alpha_j, i.e.
+ * L_kj = -(1/M_k) [ C phi_j(0) phi_k(0) / h + nu K_jk / h^2 ]  (Sec. 3.4 closure). */
+static void source_matrix(const omesh *o, double h, double *L)
+{
+    int n = o->level + 1;
+    for (int k = 0; k < n; k++)
+        for (int j = 0; j < n; j++)
+            L[k * n + j] = -(o->c_slip * o->phi0[j] * o->phi0[k] / h + o->nu * o->K[j * n + k] / (h * h)) / o->M[k];
+}
+
+/* Solve A x = r (n x n, row-major, destroyed) by Gaussian elimination with
+ * partial pivoting; x overwrites r. */
+static void gauss_solve(int n, double *A, double *r)
+{
+    for (int c = 0; c < n; c++) {
+        int piv = c;
+        for (int i = c + 1; i < n; i++)
+            if (fabs(A[i * n + c]) > fabs(A[piv * n + c])) piv = i;
+        if (piv != c) {
+            for (int j = 0; j < n; j++) {
+                double t = A[c * n + j];
+                A[c * n + j] = A[piv * n + j];
+                A[piv * n + j] = t;
+            }
+            double t = r[c];
+            r[c] = r[piv];
+            r[piv] = t;
+        }
+        for (int i = c + 1; i < n; i++) {
+            double f = A[i * n + c] / A[c * n + c];
+            for (int j = c; j < n; j++) A[i * n + j] -= f * A[c * n + j];
+            r[i] -= f * r[c];
+        }
+    }
+    for (int c = n - 1; c >= 0; c--) {
+        double v = r[c];
+        for (int j = c + 1; j < n; j++) v -= A[c * n + j] * r[j];
+        r[c] = v / A[c * n + c];
+    }
+}
+
+/* The friction ODE dq/dt = S(q) over one step dt from the predicted state
+ * qstar (h is not changed by S): forward Euler q* + dt S(q*), or backward
+ * Euler q = q* + dt S(q) solved per moment block. */
+void oracle_friction_step(const omesh *o, const double *qstar, double dt, double *out)
+{
+    int n = o->level + 1, nf = nfields(o);
+    if (!o->implicit) {
+        double src[OR_MAXF];
+        oracle_source(o, qstar, src);
+        for (int f = 0; f < nf; f++) out[f] = qstar[f] + dt * src[f];
+        return;
+    }
+    double h = qstar[0];
+    out[0] = h;
+    int nblk = (o->dim == 2) ? 2 : 1;
+    for (int d = 0; d < nblk; d++) {
+        double L[OR_MAXN * OR_MAXN], A[OR_MAXN * OR_MAXN], r[OR_MAXN];
+        source_matrix(o, h, L);
+        for (int k = 0; k < n; k++) {
+            for (int j = 0; j < n; j++) A[k * n + j] = (k == j ? 1.0 : 0.0) - dt * L[k * n + j];
+            r[k] = qstar[1 + d * n + k];
+        }
+        gauss_solve(n, A, r);
+        for (int k = 0; k < n; k++) out[1 + d * n + k] = r[k];
+    }
+}
+
 /* state and bathymetry of cell i into a local vector */
 static void load_cell(const omesh *o, const double *Q, int64_t i, double *q, double *b)
 {
@@ -263,10 +338,10 @@ void oracle_step_cells(const omesh *o, const double *Q, double dt, const int64_t
                 ghost(o, qi, bi, code, nx, ny, qj, &bj);
             face_term(o, qi, bi, qj, bj, nx, ny, len, acc);
         }
-        double qstar[OR_MAXF], src[OR_MAXF];
+        double qstar[OR_MAXF], qn[OR_MAXF];
         for (int f = 0; f < nf; f++) qstar[f] = qi[f] - dt / o->vol[i] * acc[f];
-        oracle_source(o, qstar, src);
-        for (int f = 0; f < nf; f++) out[(int64_t)f * cnt + c] = qstar[f] + dt * src[f];
+        oracle_friction_step(o, qstar, dt, qn);
+        for (int f = 0; f < nf; f++) out[(int64_t)f * cnt + c] = qn[f];
     }
 }
 
