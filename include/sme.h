@@ -187,6 +187,29 @@ int sme_level(const sme_ctx *ctx);
 const double *sme_state_device(const sme_ctx *ctx);
 int64_t sme_field_stride(const sme_ctx *ctx);
 
+/* One step without any allocation, for callers that cannot allocate device
+ * memory: code being captured into a HIP graph, tight serving loops, hosts
+ * that forbid hipMalloc.  No context: the same step as sme_step on a 1D or
+ * structured mesh (SME_EINVAL for triangles, which need geometry tables),
+ * from the caller's state q to q_next (distinct device buffers, 256-byte
+ * aligned, [nfields][field_stride] with field_stride >= ncells a multiple of
+ * 256) over the bathymetry b (device, [ncells], required).  dt > 0 is used as
+ * given; dt <= 0 takes the CFL step of q (computed on the device).  The
+ * band height on structured grids is chosen as sme_init chooses it, so the
+ * result is bitwise that of sme_step on a context holding q.
+ * Scratch: the time-step slots, the non-physical-state word and the Gauss
+ * points live in one static device array of 8 KiB per GPU (used from the
+ * first call on a device until the process ends); its size does not depend on
+ * the grid, which is limited only as sme_layout limits it.  No hipMalloc,
+ * hipFree or allocating library call is made.  Work is queued on `stream`;
+ * if dt_used is not NULL the stream is synchronised, the step taken is
+ * returned and SME_ENONPHYS reports h <= 0 or a non-finite value in q_next.
+ * Every call on a GPU shares that GPU's scratch array: calls that overlap on
+ * one GPU (other streams or host threads) race and must be serialised by the
+ * caller. */
+int sme_step_static(int level, const sme_mesh *mesh, const sme_params *params, const double *q, double *q_next,
+                    int64_t field_stride, const double *b, double dt, double *dt_used, void *stream);
+
 /* ------------------------------------------------------------------------
  * Batched ensemble: n independent structured 2D grids (SME_MESH_2D_STRUCT) of
  * mixed size and level 0..4, advanced together by one persistent kernel launch

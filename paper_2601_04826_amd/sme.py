@@ -28,7 +28,7 @@ CLOSURE_PRECISIONS = {"fp32": 0, "fp16": 1}  # SME_CLOSURE_FP32, SME_CLOSURE_FP1
 EXPORTS = [
     "sme_layout", "sme_workspace_size", "sme_init", "sme_set_state", "sme_get_state", "sme_eigmax", "sme_step",
     "sme_run", "sme_time", "sme_current", "sme_nfields", "sme_ncells", "sme_level", "sme_state_device",
-    "sme_field_stride",
+    "sme_field_stride", "sme_step_static",
     "sme_basis_tensors", "sme_strerror", "sme_last_error", "sme_destroy",
     "sme_batch_init", "sme_batch_set_state", "sme_batch_get_state", "sme_batch_run", "sme_batch_time",
     "sme_batch_cells", "sme_batch_rows", "sme_batch_set_rows", "sme_batch_autotune",
@@ -82,6 +82,7 @@ def _load():
         "sme_level": (i, [vp]),
         "sme_state_device": (vp, [vp]),
         "sme_field_stride": (i64, [vp]),
+        "sme_step_static": (i, [i, vp, vp, vp, vp, i64, vp, d, P(d), vp]),
         "sme_basis_tensors": (i, [i, vp, vp, vp, vp]),
         "sme_strerror": (ctypes.c_char_p, [i]),
         "sme_last_error": (ctypes.c_char_p, [vp]),
@@ -266,6 +267,21 @@ def sme_time(ctx):
 
 def sme_destroy(ctx):
     _lib.sme_destroy(ctx)
+
+
+def sme_step_static(level, mesh, params, q, q_next, b, dt=0.0, stream=None):
+    """One step from q to q_next (torch CUDA float64 [nfields, field_stride]) over
+    b (torch CUDA float64, 256-byte aligned) with no allocation; returns dt."""
+    for x in (q, q_next, b):
+        if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.float64 and x.is_contiguous()):
+            raise TypeError("q, q_next and b must be contiguous float64 CUDA tensors")
+    if stream is None:
+        stream = torch.cuda.current_stream().cuda_stream
+    used = ctypes.c_double()
+    _check(_lib.sme_step_static(level, ctypes.byref(mesh), ctypes.byref(params), ctypes.c_void_p(q.data_ptr()),
+                                ctypes.c_void_p(q_next.data_ptr()), q.shape[1], ctypes.c_void_p(b.data_ptr()),
+                                float(dt), ctypes.byref(used), ctypes.c_void_p(stream or 0)))
+    return used.value
 
 
 def sme_basis_tensors(level):
