@@ -77,13 +77,17 @@ typedef struct sme_ctx sme_ctx;
  * kinematic viscosity of the Newtonian bulk closure (m^2/s); cfl the Courant
  * number of the adaptive step (0.45 in the paper); quad_points the number of
  * Gauss-Legendre points (1..8) on the straight path of the non-conservative
- * fluctuation. */
+ * fluctuation; implicit_friction selects how the friction ODE of the
+ * splitting (Eq. (3d)) is stepped: 0 forward Euler on the predicted state,
+ * 1 backward Euler (the cell-local linear solve per moment block, stable for
+ * any nu dt / h^2: the implicit source step of Sec. 2.1.2). */
 typedef struct {
     double g;
     double c_slip;
     double nu;
     double cfl;
     int quad_points;
+    int implicit_friction;
 } sme_params;
 
 /* Mesh description; all arrays are host memory, copied during sme_init.

@@ -18,6 +18,8 @@ using namespace detail;
 
 namespace {
 
+// IMP: the friction step is backward Euler (compile-time copy of the flag)
+template <bool IMP>
 __global__ __launch_bounds__(kBlock) void k_batch_step(BatchArgs B)
 {
     const int lane = threadIdx.x & (kWave - 1);
@@ -49,6 +51,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_step(BatchArgs B)
         a.fnx = a.fny = a.fw = nullptr;
         a.g = B.g;
         a.c_slip = B.c_slip;
+        a.implicit = B.implicit;
         a.nu = B.nu;
         a.cfl = B.cfl;
         a.quad = B.quad;
@@ -66,11 +69,11 @@ __global__ __launch_bounds__(kBlock) void k_batch_step(BatchArgs B)
         if (item.sx == 0 && item.sy == 0 && lane == 0) slot_update(a, dt);
         double r = 0.0;
         switch (I.level) {
-        case 0: r = band2d<0>(a, dt, item.sx, item.sy, stage); break;
-        case 1: r = band2d<1>(a, dt, item.sx, item.sy, stage); break;
-        case 2: r = band2d<2>(a, dt, item.sx, item.sy, stage); break;
-        case 3: r = band2d<3>(a, dt, item.sx, item.sy, stage); break;
-        case 4: r = band2d<4>(a, dt, item.sx, item.sy, stage); break;
+        case 0: r = band2d<0, false, IMP>(a, dt, item.sx, item.sy, stage); break;
+        case 1: r = band2d<1, false, IMP>(a, dt, item.sx, item.sy, stage); break;
+        case 2: r = band2d<2, false, IMP>(a, dt, item.sx, item.sy, stage); break;
+        case 3: r = band2d<3, false, IMP>(a, dt, item.sx, item.sy, stage); break;
+        case 4: r = band2d<4, false, IMP>(a, dt, item.sx, item.sy, stage); break;
         default: break;
         }
         r = wave_max(r);
@@ -83,7 +86,10 @@ __global__ __launch_bounds__(kBlock) void k_batch_step(BatchArgs B)
 
 hipError_t launch_batch_step(const BatchArgs &a, int grid, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_batch_step, dim3(grid), dim3(kBlock), 0, s, a);
+    if (a.implicit)
+        hipLaunchKernelGGL(k_batch_step<true>, dim3(grid), dim3(kBlock), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_batch_step<false>, dim3(grid), dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
 
@@ -92,7 +98,7 @@ hipError_t launch_batch_step(const BatchArgs &a, int grid, hipStream_t s)
 int batch_waves_per_simd()
 {
     int blocks = 0;
-    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch_step, kBlock, 0);
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch_step<false>, kBlock, 0);
     return e == hipSuccess && blocks > 0 ? blocks * (kBlock / kWave) / 4 : 1;
 }
 

@@ -20,7 +20,7 @@ namespace {
 // shift, the left face's share from the lane below.  Returns h of Q^{n+1}
 // and writes its momenta to q and 1/h to ih.  Shared by the step kernel and
 // the multi-step kernel, so both give bitwise equal states.
-template <int N>
+template <int N, bool IMP>
 __device__ __forceinline__ double update_1d(const StepArgs &a, double dt, const Side<N, false> &S, double *q,
                                             double &ih)
 {
@@ -48,11 +48,13 @@ __device__ __forceinline__ double update_1d(const StepArgs &a, double dt, const 
 #pragma unroll
     for (int k = 0; k < n; ++k) q[k] = fma(-sc, acc[1 + k], S.qa[k]);
     ih = rcp(h);
-    friction<N>(q, ih, dt, a.c_slip, a.nu);
+    friction_step<N, false, IMP>(q, nullptr, ih, dt, a.c_slip, a.nu);
     return h;
 }
 
-template <int N, bool CLOS>
+// IMP: the friction step is backward Euler (a compile-time copy of the flag,
+// so the explicit kernels keep their own register allocation)
+template <int N, bool CLOS, bool IMP>
 __global__ __launch_bounds__(kBlock) void k_step_1d(StepArgs a)
 {
     constexpr int n = N + 1;
@@ -83,7 +85,7 @@ __global__ __launch_bounds__(kBlock) void k_step_1d(StepArgs a)
         side_flux<N, false>(S, a.g);
         // faces, predictor and friction
         double q[n], ih;
-        const double h = update_1d<N>(a, dt, S, q, ih);
+        const double h = update_1d<N, IMP>(a, dt, S, q, ih);
         if constexpr (CLOS) {
             static_assert(N == 1, "the closure acts on level 1");
             if (out) {  // rates of (q_0, q_1) from the rates pass over Q^n
@@ -120,7 +122,7 @@ __global__ __launch_bounds__(kBlock) void k_step_1d(StepArgs a)
 // nsteps steps) and the time slots are left as nsteps steps would leave them.
 constexpr int kRunBlock = 1024;
 
-template <int N>
+template <int N, bool IMP>
 __global__ __launch_bounds__(kRunBlock) void k_run_1d_lds(StepArgs a, int nsteps, double *dst)
 {
     constexpr int n = N + 1;
@@ -168,7 +170,7 @@ __global__ __launch_bounds__(kRunBlock) void k_run_1d_lds(StepArgs a, int nsteps
             }
             side_flux<N, false>(S, a.g);
             double q[n], ih;
-            const double h = update_1d<N>(a, dt, S, q, ih);
+            const double h = update_1d<N, IMP>(a, dt, S, q, ih);
             if (o) {
                 out[c] = h;
                 bool bad = !(h > 0.0) || !isfinite(h);
@@ -228,12 +230,20 @@ hipError_t launch_run_1d_lds(int level, const StepArgs &a, int nsteps, double *d
 {
     const size_t bytes = run_1d_lds_bytes(level, a.nx);
     hipError_t e = hipSuccess;
-#define R1(N)                                                                                                    \
-    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_run_1d_lds<N>),                                     \
+#define R1I(N, I)                                                                                                \
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_run_1d_lds<N, I>),                                  \
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);                              \
-    if (e == hipSuccess) hipLaunchKernelGGL(k_run_1d_lds<N>, dim3(1), dim3(kRunBlock), bytes, s, a, nsteps, dst)
-    SME_LEVEL_SWITCH(level, R1)
+    if (e == hipSuccess) hipLaunchKernelGGL((k_run_1d_lds<N, I>), dim3(1), dim3(kRunBlock), bytes, s, a, nsteps, dst)
+#define R1(N) R1I(N, false)
+#define R1X(N) R1I(N, true)
+    if (a.implicit) {
+        SME_LEVEL_SWITCH(level, R1X)
+    } else {
+        SME_LEVEL_SWITCH(level, R1)
+    }
 #undef R1
+#undef R1X
+#undef R1I
     return e == hipSuccess ? hipGetLastError() : e;
 }
 
@@ -243,12 +253,21 @@ hipError_t launch_step_1d(int level, const StepArgs &a, hipStream_t s)
     const unsigned grid = blocks_for(waves * kWave);
     if (a.closure) {
         if (level != 1) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((k_step_1d<1, true>), dim3(grid), dim3(kBlock), 0, s, a);
+        if (a.implicit)
+            hipLaunchKernelGGL((k_step_1d<1, true, true>), dim3(grid), dim3(kBlock), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_step_1d<1, true, false>), dim3(grid), dim3(kBlock), 0, s, a);
         return hipGetLastError();
     }
-#define L1(N) hipLaunchKernelGGL((k_step_1d<N, false>), dim3(grid), dim3(kBlock), 0, s, a)
-    SME_LEVEL_SWITCH(level, L1)
+#define L1(N) hipLaunchKernelGGL((k_step_1d<N, false, false>), dim3(grid), dim3(kBlock), 0, s, a)
+#define L1X(N) hipLaunchKernelGGL((k_step_1d<N, false, true>), dim3(grid), dim3(kBlock), 0, s, a)
+    if (a.implicit) {
+        SME_LEVEL_SWITCH(level, L1X)
+    } else {
+        SME_LEVEL_SWITCH(level, L1)
+    }
 #undef L1
+#undef L1X
     return hipGetLastError();
 }
 

@@ -16,7 +16,9 @@ constexpr int waves_target()
     return N == 2 ? 3 : (N == 4 ? 2 : 1);
 }
 
-template <int N, bool CLOS>
+// IMP: the friction step is backward Euler (a compile-time copy of the flag,
+// so the explicit kernels keep their own register allocation)
+template <int N, bool CLOS, bool IMP>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(waves_target<N>()))) void k_step_2d(StepArgs a)
 {
     const double dt = step_dt(a);
@@ -39,7 +41,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(waves_ta
     __shared__ __attribute__((aligned(16))) double stage[(kBlock / kWave) * sd];
     double rmax = 0.0;
     if (wave < nsx * nsy)  // waves beyond the grid only join the reduction
-        rmax = band2d<N, CLOS>(a, dt, wave % nsx, wave / nsx, stage + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) * sd);
+        rmax = band2d<N, CLOS, IMP>(a, dt, wave % nsx, wave / nsx, stage + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) * sd);
     publish_ratio(a.slots[a.sb], rmax);
 }
 
@@ -54,12 +56,21 @@ hipError_t launch_step_2d(int level, const StepArgs &a, hipStream_t s)
     const unsigned grid = (unsigned)((blocks + kXcd - 1) / kXcd * kXcd);
     if (a.closure) {
         if (level != 1) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((k_step_2d<1, true>), dim3(grid), dim3(kBlock), 0, s, a);
+        if (a.implicit)
+            hipLaunchKernelGGL((k_step_2d<1, true, true>), dim3(grid), dim3(kBlock), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_step_2d<1, true, false>), dim3(grid), dim3(kBlock), 0, s, a);
         return hipGetLastError();
     }
-#define L2(N) hipLaunchKernelGGL((k_step_2d<N, false>), dim3(grid), dim3(kBlock), 0, s, a)
-    SME_LEVEL_SWITCH(level, L2)
+#define L2(N) hipLaunchKernelGGL((k_step_2d<N, false, false>), dim3(grid), dim3(kBlock), 0, s, a)
+#define L2X(N) hipLaunchKernelGGL((k_step_2d<N, false, true>), dim3(grid), dim3(kBlock), 0, s, a)
+    if (a.implicit) {
+        SME_LEVEL_SWITCH(level, L2X)
+    } else {
+        SME_LEVEL_SWITCH(level, L2)
+    }
 #undef L2
+#undef L2X
     return hipGetLastError();
 }
 
@@ -70,7 +81,7 @@ int step_2d_waves_per_simd(int level)
 {
     int blocks = 0;
     hipError_t e = hipErrorInvalidValue;
-#define O2(N) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_step_2d<N, false>, kBlock, 0)
+#define O2(N) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_step_2d<N, false, false>, kBlock, 0)
     switch (level) {
     case 0: O2(0); break;
     case 1: O2(1); break;

@@ -52,7 +52,8 @@ __device__ __forceinline__ void gather(const StepArgs &a, int j, int64_t gi, Gat
     }
 }
 
-template <int N>
+// IMP: the friction step is backward Euler (compile-time copy of the flag)
+template <int N, bool IMP>
 __global__ __launch_bounds__(kBlock) void k_step_tri(StepArgs a)
 {
     constexpr int n = N + 1;
@@ -152,8 +153,7 @@ __global__ __launch_bounds__(kBlock) void k_step_tri(StepArgs a)
             qy[k] = fma(-dt, acc[1 + n + k], qy0[k]);
         }
         const double ih = rcp(h);
-        friction<N>(qx, ih, dt, a.c_slip, a.nu);
-        friction<N>(qy, ih, dt, a.c_slip, a.nu);
+        friction_step<N, true, IMP>(qx, qy, ih, dt, a.c_slip, a.nu);
         a.qn[i] = h;
         bool bad = !(h > 0.0) || !isfinite(h);
 #pragma unroll
@@ -183,9 +183,15 @@ hipError_t launch_step_tri(int level, const StepArgs &a, hipStream_t s)
 {
     // whole dies' worth of blocks, so the die-major slot order covers every cell
     const unsigned grid = (blocks_for(a.ncells) + kXcd - 1) / kXcd * kXcd;
-#define L3(N) hipLaunchKernelGGL(k_step_tri<N>, dim3(grid), dim3(kBlock), 0, s, a)
-    SME_LEVEL_SWITCH(level, L3)
+#define L3(N) hipLaunchKernelGGL((k_step_tri<N, false>), dim3(grid), dim3(kBlock), 0, s, a)
+#define L3X(N) hipLaunchKernelGGL((k_step_tri<N, true>), dim3(grid), dim3(kBlock), 0, s, a)
+    if (a.implicit) {
+        SME_LEVEL_SWITCH(level, L3X)
+    } else {
+        SME_LEVEL_SWITCH(level, L3)
+    }
 #undef L3
+#undef L3X
     return hipGetLastError();
 }
 

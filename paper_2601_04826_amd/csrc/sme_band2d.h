@@ -248,7 +248,7 @@ __device__ __forceinline__ void x_faces(const StepArgs &a, const Cell2<N> &C, do
 }
 
 // predictor, friction, store, CFL ratio of the new state
-template <int N, bool CLOS>
+template <int N, bool CLOS, bool IMP>
 __device__ __forceinline__ double finish_cell(const StepArgs &a, double dt, int64_t cell, bool out,
                                               const Cell2<N> &c, const double *acc)
 {
@@ -261,8 +261,7 @@ __device__ __forceinline__ double finish_cell(const StepArgs &a, double dt, int6
         qy[k] = fma(-dt, acc[1 + n + k], c.qy[k]);
     }
     const double ih = rcp(h);
-    friction<N>(qx, ih, dt, a.c_slip, a.nu);
-    friction<N>(qy, ih, dt, a.c_slip, a.nu);
+    friction_step<N, true, IMP>(qx, qy, ih, dt, a.c_slip, a.nu);
     if constexpr (CLOS) {
         // learned closure: rates of (q_0, q_1) normal to x and to y from the rates pass
         if (out) {
@@ -294,32 +293,32 @@ __device__ __forceinline__ double finish_cell(const StepArgs &a, double dt, int6
 
 // one row: C <- row j (state in `raw`), y-face with P, finish P (row j-1) if
 // requested, x-faces of C.
-template <int N, bool CLOS>
+template <int N, bool CLOS, bool IMP>
 __device__ __forceinline__ void row(const StepArgs &a, double dt, Cell2<N> &P, double *accP, Cell2<N> &C,
                                     double *accC, const Raw2<N> &raw, int j, int c, bool outc, bool finish_p,
                                     double &rmax)
 {
     cell_flux<N>(C, raw, a.g);
     y_face<N, true>(a, P, C, accP, accC, finish_p);
-    if (finish_p) rmax = fmax(rmax, finish_cell<N, CLOS>(a, dt, (int64_t)(j - 1) * a.nx + c, outc, P, accP));
+    if (finish_p) rmax = fmax(rmax, finish_cell<N, CLOS, IMP>(a, dt, (int64_t)(j - 1) * a.nx + c, outc, P, accP));
     x_faces<N>(a, C, accC);
 }
 
 // closing y-face of the band: P is the last row (j1 - 1), raw the row above
-template <int N, bool CLOS>
+template <int N, bool CLOS, bool IMP>
 __device__ __forceinline__ void close_band(const StepArgs &a, double dt, Cell2<N> &P, double *accP,
                                            Cell2<N> &G, const Raw2<N> &raw, int j1, int c, bool outc,
                                            double &rmax)
 {
     cell_flux<N>(G, raw, a.g);
     y_face<N, false>(a, P, G, accP, nullptr, true);
-    rmax = fmax(rmax, finish_cell<N, CLOS>(a, dt, (int64_t)(j1 - 1) * a.nx + c, outc, P, accP));
+    rmax = fmax(rmax, finish_cell<N, CLOS, IMP>(a, dt, (int64_t)(j1 - 1) * a.nx + c, outc, P, accP));
 }
 
 // Whole band (strip sx, band sy) of one grid: returns the largest CFL ratio
 // of the cells it wrote.  All 64 lanes of the wave must call it.  stage is
 // this wave's staging area (stage_doubles<N>() doubles of LDS).
-template <int N, bool CLOS = false>
+template <int N, bool CLOS = false, bool IMP = false>
 __device__ __forceinline__ double band2d(const StepArgs &a, double dt, int sx, int sy, double *stage)
 {
     constexpr int n = N + 1;
@@ -351,20 +350,20 @@ __device__ __forceinline__ double band2d(const StepArgs &a, double dt, int sx, i
         // buf0's previous row was read into registers before its arithmetic
         read_row<N>(a, j, mx, buf1, cur);
         stage_row<N>(a, j + 1, voff, buf0);  // next row, or the closing halo row
-        row<N, CLOS>(a, dt, A, accA, B, accB, cur, j, c, outc, j > j0, rmax);
+        row<N, CLOS, IMP>(a, dt, A, accA, B, accB, cur, j, c, outc, j > j0, rmax);
         wait_staged();
         if (++j == j1) {
             read_row<N>(a, j1, mx, buf0, cur);
-            close_band<N, CLOS>(a, dt, B, accB, A, cur, j1, c, outc, rmax);
+            close_band<N, CLOS, IMP>(a, dt, B, accB, A, cur, j1, c, outc, rmax);
             break;
         }
         read_row<N>(a, j, mx, buf0, cur);
         stage_row<N>(a, j + 1, voff, buf1);
-        row<N, CLOS>(a, dt, B, accB, A, accA, cur, j, c, outc, true, rmax);
+        row<N, CLOS, IMP>(a, dt, B, accB, A, accA, cur, j, c, outc, true, rmax);
         wait_staged();
         if (++j == j1) {
             read_row<N>(a, j1, mx, buf1, cur);
-            close_band<N, CLOS>(a, dt, A, accA, B, cur, j1, c, outc, rmax);
+            close_band<N, CLOS, IMP>(a, dt, A, accA, B, cur, j1, c, outc, rmax);
             break;
         }
     }

@@ -182,4 +182,97 @@ struct Basis {
     static constexpr Tensors<N> T = make_tensors<N>();
 };
 
+// ---------------------------------------------------------------------------
+// Modes of the bulk friction for its implicit step.  With M = diag(M_k) the
+// generalized eigenproblem K v = mu M v has M-orthonormal eigenvectors: the
+// symmetric G = M^{-1/2} K M^{-1/2} = V diag(mu) V^T (V orthogonal), and
+// P = M^{-1/2} V satisfies P^T M P = I, P^T K P = diag(mu).  Then
+//   (M + e K)^{-1} = P diag(1 / (1 + e mu)) P^T,
+// so a solve with M + e K needs only the constant matrices P and R = P^T M
+// (= V^T M^{1/2}) and one reciprocal per mode.  K couples only moments of
+// equal parity and K_0k = 0, so V is block-sparse by parity and the mean
+// mode (mu = 0) is e_0.  G is diagonalised at compile time by cyclic Jacobi
+// rotations in double precision; w = P^T 1 serves the rank-one slip term.
+constexpr double csqrt(double a)
+{
+    if (!(a > 0.0)) return 0.0;
+    double x = a > 1.0 ? a : 1.0;  // Newton from above decreases monotonically
+    for (int i = 0; i < 400; ++i) {
+        const double nx = 0.5 * (x + a / x);
+        if (!(nx < x)) break;
+        x = nx;
+    }
+    return x;
+}
+
+constexpr double cabs(double a) { return a < 0.0 ? -a : a; }
+
+template <int N>
+struct FrictionModes {
+    static constexpr int n = N + 1;
+    double mu[n];     // eigenvalues of K v = mu M v
+    double P[n][n];   // P[j][m]: component j of mode m (M-orthonormal)
+    double R[n][n];   // R[m][j] = (P^T M)[m][j]: modal coordinate m of a momentum vector
+    double w[n];      // w[m] = sum_j P[j][m]
+};
+
+template <int N>
+constexpr FrictionModes<N> make_modes()
+{
+    constexpr int n = N + 1;
+    const auto &T = Basis<N>::T;
+    double G[n][n] = {}, V[n][n] = {}, sq[n] = {};
+    for (int k = 0; k < n; ++k) sq[k] = csqrt((double)(2 * k + 1));  // M_k^{-1/2}
+    for (int j = 0; j < n; ++j)
+        for (int k = 0; k < n; ++k) {
+            G[j][k] = T.K[j][k] * sq[j] * sq[k];
+            V[j][k] = j == k ? 1.0 : 0.0;
+        }
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        double off = 0.0, diag = 0.0;
+        for (int p = 0; p < n; ++p)
+            for (int q = 0; q < n; ++q) (p == q ? diag : off) += G[p][q] * G[p][q];
+        if (off <= 1e-34 * diag) break;
+        for (int p = 0; p < n; ++p)
+            for (int q = p + 1; q < n; ++q) {
+                if (G[p][q] == 0.0) continue;
+                const double th = (G[q][q] - G[p][p]) / (2.0 * G[p][q]);
+                const double t = (th >= 0.0 ? 1.0 : -1.0) / (cabs(th) + csqrt(th * th + 1.0));
+                const double c = 1.0 / csqrt(t * t + 1.0), s = t * c;
+                for (int k = 0; k < n; ++k) {  // G <- G J (columns p, q)
+                    const double gp = G[k][p], gq = G[k][q];
+                    G[k][p] = c * gp - s * gq;
+                    G[k][q] = s * gp + c * gq;
+                }
+                for (int k = 0; k < n; ++k) {  // G <- J^T G (rows p, q)
+                    const double gp = G[p][k], gq = G[q][k];
+                    G[p][k] = c * gp - s * gq;
+                    G[q][k] = s * gp + c * gq;
+                }
+                G[p][q] = G[q][p] = 0.0;
+                for (int k = 0; k < n; ++k) {  // V <- V J
+                    const double vp = V[k][p], vq = V[k][q];
+                    V[k][p] = c * vp - s * vq;
+                    V[k][q] = s * vp + c * vq;
+                }
+            }
+    }
+    FrictionModes<N> f{};
+    for (int m = 0; m < n; ++m) {
+        f.mu[m] = G[m][m];
+        f.w[m] = 0.0;
+        for (int j = 0; j < n; ++j) {
+            f.P[j][m] = sq[j] * V[j][m];
+            f.R[m][j] = V[j][m] / sq[j];
+            f.w[m] += f.P[j][m];
+        }
+    }
+    return f;
+}
+
+template <int N>
+struct Modes {
+    static constexpr FrictionModes<N> F = make_modes<N>();
+};
+
 }  // namespace sme

@@ -314,4 +314,76 @@ __device__ __forceinline__ void friction(double *q, double ih, double dt, double
     });
 }
 
+// Friction ODE (same source S) by one backward-Euler step: q solves
+//   q = q* + dt S(q)   <=>   (M + c 1 1^T + e K) q = M q*,   c = C dt / h, e = nu dt / h^2
+// per moment block (h is not changed by S).  With the friction modes
+// (M + e K)^{-1} = P diag(g) P^T, g_m = 1 / (1 + e mu_m), and the rank-one
+// slip term by Sherman-Morrison:
+//   z = g o (R q*),  beta = c (w . z) / (1 + c sum_m w_m^2 g_m),  q = P (z - beta g o w).
+// The matrix is symmetric positive definite for any dt, so the step is stable
+// at any nu dt / h^2 (no stiffness limit).  TWO: qy holds a second block.
+template <int N, bool TWO>
+__device__ __forceinline__ void friction_implicit(double *qx, double *qy, double ih, double dt, double c_slip,
+                                                  double nu)
+{
+    constexpr int n = N + 1;
+    using F = Modes<N>;  // F::F holds mu, P, R, w
+    const double c = dt * c_slip * ih;
+    const double e = dt * nu * (ih * ih);
+    double g[n];
+    double s2 = 0.0;
+    sfor<0, n>([&](auto Mi) {
+        constexpr int m = decltype(Mi)::value;
+        if constexpr (F::F.mu[m] == 0.0)
+            g[m] = 1.0;
+        else
+            g[m] = rcp(fma(e, F::F.mu[m], 1.0));
+        s2 = fma(F::F.w[m] * F::F.w[m], g[m], s2);
+    });
+    const double ic = rcp(fma(c, s2, 1.0));
+    auto solve = [&](double *q) {
+        double z[n];
+        double s1 = 0.0;
+        sfor<0, n>([&](auto Mi) {
+            constexpr int m = decltype(Mi)::value;
+            double y = 0.0;
+            sfor<0, n>([&](auto J) {
+                constexpr int j = decltype(J)::value;
+                if constexpr (F::F.R[m][j] != 0.0) y = fma(F::F.R[m][j], q[j], y);
+            });
+            z[m] = g[m] * y;
+            s1 = fma(F::F.w[m], z[m], s1);
+        });
+        const double beta = c * s1 * ic;
+        sfor<0, n>([&](auto Mi) {
+            constexpr int m = decltype(Mi)::value;
+            z[m] = fma(-beta * F::F.w[m], g[m], z[m]);
+        });
+        sfor<0, n>([&](auto J) {
+            constexpr int j = decltype(J)::value;
+            double v = 0.0;
+            sfor<0, n>([&](auto Mi) {
+                constexpr int m = decltype(Mi)::value;
+                if constexpr (F::F.P[j][m] != 0.0) v = fma(F::F.P[j][m], z[m], v);
+            });
+            q[j] = v;
+        });
+    };
+    solve(qx);
+    if constexpr (TWO) solve(qy);
+}
+
+// The friction step of the splitting on one cell: explicit (forward Euler)
+// or implicit (backward Euler, IMP); a kernel instantiation takes one of them.
+template <int N, bool TWO, bool IMP>
+__device__ __forceinline__ void friction_step(double *qx, double *qy, double ih, double dt, double c_slip, double nu)
+{
+    if constexpr (IMP) {
+        friction_implicit<N, TWO>(qx, qy, ih, dt, c_slip, nu);
+    } else {
+        friction<N>(qx, ih, dt, c_slip, nu);
+        if constexpr (TWO) friction<N>(qy, ih, dt, c_slip, nu);
+    }
+}
+
 }  // namespace sme

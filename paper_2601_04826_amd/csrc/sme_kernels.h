@@ -65,6 +65,7 @@ struct StepArgs {
     const double *fnx, *fny, *fw;  // [3][stride], fw = |e| / |V|
     // model
     double g, c_slip, nu, cfl;
+    int implicit;        // friction step: 0 forward Euler, 1 backward Euler
     Quad quad;
     // time stepping
     double dt_fixed;     // > 0: fixed step
@@ -107,6 +108,7 @@ struct BatchArgs {
     int sa, sb, sc;
     ErrWord *err;
     double g, c_slip, nu, cfl;
+    int implicit;
     Quad quad;
 };
 

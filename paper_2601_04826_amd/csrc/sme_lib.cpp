@@ -326,6 +326,7 @@ StepArgs make_args(const sme_ctx *c)
     a.fw = c->fw;
     a.g = c->p.g;
     a.c_slip = c->p.c_slip;
+    a.implicit = c->p.implicit_friction;
     a.nu = c->p.nu;
     a.cfl = c->p.cfl;
     a.quad = c->quad;
@@ -471,7 +472,7 @@ int sme_init(sme_ctx **out, int level, const sme_mesh *mesh, const sme_params *p
     int r = check_mesh(mesh, level, &nf, &nc);
     if (r != SME_OK) return r;
     if (params->quad_points < 1 || params->quad_points > kMaxQuad || !(params->cfl > 0) || !(params->g > 0) ||
-        params->c_slip < 0 || params->nu < 0)
+        params->c_slip < 0 || params->nu < 0 || (params->implicit_friction != 0 && params->implicit_friction != 1))
         return SME_EINVAL;
     sme_ctx *c = new (std::nothrow) sme_ctx();
     if (!c) return SME_ENOMEM;

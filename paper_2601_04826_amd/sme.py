@@ -43,7 +43,7 @@ EXPORTS = [
 
 class sme_params(ctypes.Structure):
     _fields_ = [("g", ctypes.c_double), ("c_slip", ctypes.c_double), ("nu", ctypes.c_double),
-                ("cfl", ctypes.c_double), ("quad_points", ctypes.c_int)]
+                ("cfl", ctypes.c_double), ("quad_points", ctypes.c_int), ("implicit_friction", ctypes.c_int)]
 
 
 class sme_mesh(ctypes.Structure):
@@ -148,8 +148,8 @@ def _ptr(a):
     return a.ctypes.data_as(ctypes.c_void_p), False
 
 
-def make_params(g=9.81, c_slip=0.0, nu=0.0, cfl=0.45, quad_points=3):
-    return sme_params(g, c_slip, nu, cfl, quad_points)
+def make_params(g=9.81, c_slip=0.0, nu=0.0, cfl=0.45, quad_points=3, implicit_friction=0):
+    return sme_params(g, c_slip, nu, cfl, quad_points, int(implicit_friction))
 
 
 def make_mesh(problem):
