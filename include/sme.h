@@ -114,7 +114,7 @@ int sme_layout(int level, const sme_mesh *mesh, int *nfields, int64_t *ncells, i
 
 /* Bytes of device memory sme_init allocates for a (level, mesh) pair besides
  * the caller's state buffers: bathymetry, Gauss points, time-step slots and,
- * on triangles, neighbours, normals and the two cell permutations.  Attaching
+ * on triangles, neighbours, normals, centroids and the two cell permutations.  Attaching
  * a learned closure adds its network and rates buffers. */
 int sme_workspace_size(int level, const sme_mesh *mesh, size_t *bytes);
 
@@ -175,6 +175,24 @@ int sme_run(sme_ctx *ctx, int64_t n_steps, double t_end, double *t_out, int64_t 
 
 /* Simulated time and step count since sme_set_state (synchronises). */
 int sme_time(sme_ctx *ctx, double *t, int64_t *steps);
+
+/* 3D lifting of the current state (the interpolate_3d postprocessing of
+ * Sec. 2.2.1; the shallow-water case is printed in Sec. 3.1): for nz sigma
+ * levels zeta[l] in [0, 1] (host array, nz <= 64) and every cell, writes into
+ * the device array out [5][nz][ncells] (caller cell order) the variables
+ *   z = b + zeta h                                   elevation of the level
+ *   u = sum_k alpha_k phi_k(zeta), v = sum_k beta_k phi_k(zeta)   (v = 0 in 1D)
+ *   w = -sum_k (d_x qx_k + d_y qy_k) Phi_k(zeta) + u (d_x b + zeta d_x h)
+ *       + v (d_y b + zeta d_y h)                     incompressibility with the
+ *                                                    kinematic bed condition
+ *   p = rho g h (1 - zeta)                           hydrostatic pressure
+ * Horizontal derivatives are least-squares gradients over the cell's
+ * neighbours inside the domain (central differences on uniform grids, one-sided
+ * at walls and open ends; the minimum-norm gradient for a triangle with one
+ * neighbour).  rho > 0 (1 gives the kinematic pressure).  Queued on the
+ * context's stream; SME_EINVAL for a bad level count, a level outside [0, 1]
+ * or an output that is not device memory. */
+int sme_interpolate_3d(sme_ctx *ctx, int nz, const double *zeta, double rho, double *out);
 
 /* Which of the two bound buffers (0 or 1, the index into q_dev of sme_init)
  * holds the current state; it alternates with every step. */

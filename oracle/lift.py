@@ -44,18 +44,20 @@ def _phi_and_Phi(level, zeta):
     return np.array(phi), np.array(Phi)
 
 
-def lsq_gradients(m, F, spacing=None):
+def lsq_gradients(m, F, spacing=None, cells=None):
     """Least-squares gradients of the rows of F ([nfield, ncells]) on mesh m.
 
     spacing: (dx, dy) of a uniform 1D or structured grid; the displacement
     across a face is then its outward normal times the spacing (which also
     holds across a periodic boundary).  None: centre-to-centre displacements
-    (triangles).  Returns G [nfield, ncells, dim]."""
+    (triangles).  cells: only these cells (default all).
+    Returns G [nfield, len(cells), dim]."""
     nf, nc = F.shape
     dim = m.dim
-    G = np.zeros((nf, nc, dim))
+    cells = np.arange(nc) if cells is None else np.asarray(cells)
+    G = np.zeros((nf, len(cells), dim))
     cen = np.asarray(m.centers, dtype=np.float64).reshape(nc, -1)
-    for i in range(nc):
+    for c, i in enumerate(cells):
         rows, rhs = [], []
         for s in range(m.maxf):
             j = m.nbr[i, s]
@@ -72,13 +74,14 @@ def lsq_gradients(m, F, spacing=None):
         A = np.array(rows)
         R = np.array(rhs)                     # [nnbr, nfield]
         g, *_ = np.linalg.lstsq(A, R, rcond=None)
-        G[:, i, :] = g.T
+        G[:, c, :] = g.T
     return G
 
 
-def interpolate_3d(level, m, Q, b, zeta, rho=1.0, g=9.81, spacing=None):
+def interpolate_3d(level, m, Q, b, zeta, rho=1.0, g=9.81, spacing=None, cells=None):
     """Lifted fields at the sigma levels zeta: dict of z, u, v, w, p, each
-    [len(zeta), ncells] (v = 0 in 1D)."""
+    [len(zeta), ncells] (v = 0 in 1D); cells: only these cells (columns in
+    that order)."""
     zeta = np.asarray(zeta, dtype=np.float64)
     n = level + 1
     Q = np.asarray(Q, dtype=np.float64)
@@ -87,7 +90,9 @@ def interpolate_3d(level, m, Q, b, zeta, rho=1.0, g=9.81, spacing=None):
     qy = Q[1 + n:1 + 2 * n] if m.dim == 2 else np.zeros_like(qx)
     b = np.zeros(h.shape) if b is None else np.asarray(b, dtype=np.float64)
     fields = np.vstack([h[None], b[None], qx, qy])
-    G = lsq_gradients(m, fields, spacing)
+    G = lsq_gradients(m, fields, spacing, cells)
+    if cells is not None:
+        h, b, qx, qy = h[cells], b[cells], qx[:, cells], qy[:, cells]
     gx = G[..., 0]
     gy = G[..., 1] if m.dim == 2 else np.zeros_like(gx)
     dh_x, db_x, dqx_x = gx[0], gx[1], gx[2:2 + n]

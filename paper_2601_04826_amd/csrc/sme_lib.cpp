@@ -20,6 +20,7 @@
 #include "../../include/sme.h"
 #include "sme_host.h"
 #include "sme_kernels.h"
+#include "sme_lift.h"
 
 using namespace sme;
 
@@ -65,6 +66,7 @@ struct sme_ctx {
     double *b = nullptr;
     int32_t *nbr = nullptr;
     double *fnx = nullptr, *fny = nullptr, *fw = nullptr;
+    double *cx = nullptr, *cy = nullptr;  // triangle centroids (3D lifting)
     int64_t *to_internal = nullptr;  // caller cell -> internal cell (triangles)
     int64_t *to_caller = nullptr;    // internal cell -> caller cell
     Slot *slots = nullptr;
@@ -457,6 +459,7 @@ int sme_workspace_size(int level, const sme_mesh *mesh, size_t *bytes)
                + 3 * sizeof(Slot) + sizeof(ErrWord) + 2 * kMaxQuad * sizeof(double);
     if (mesh->kind == SME_MESH_2D_TRI)
         n += 3 * st * (sizeof(int32_t) + 3 * sizeof(double))  // neighbours, normals, |e|/|V|
+             + 2 * st * sizeof(double)                        // centroids
              + 2 * (size_t)nc * sizeof(int64_t);             // the two permutations
     *bytes = n;
     return SME_OK;
@@ -551,8 +554,13 @@ int sme_init(sme_ctx **out, int level, const sme_mesh *mesh, const sme_params *p
             for (int64_t k = 0; k < nc; ++k) inv[order[k]] = k;
             std::vector<int32_t> nb(3 * c->stride, -1);
             std::vector<double> fx(3 * c->stride, 0.0), fy(3 * c->stride, 0.0), fw(3 * c->stride, 0.0);
+            std::vector<double> ccx(c->stride, 0.0), ccy(c->stride, 0.0);
             for (int64_t k = 0; k < nc; ++k) {
                 int64_t t = order[k];
+                for (int s = 0; s < 3; ++s) {
+                    ccx[k] += mesh->vert_xy[2 * mesh->tri[3 * t + s]] / 3.0;
+                    ccy[k] += mesh->vert_xy[2 * mesh->tri[3 * t + s] + 1] / 3.0;
+                }
                 for (int s = 0; s < 3; ++s) {
                     int32_t v = g.nbr[3 * t + s];
                     nb[s * c->stride + k] = v >= 0 ? (int32_t)inv[v] : -1;
@@ -567,6 +575,8 @@ int sme_init(sme_ctx **out, int level, const sme_mesh *mesh, const sme_params *p
             rc = rc ? rc : dalloc(c, &c->fw, 3 * c->stride);
             rc = rc ? rc : dalloc(c, &c->to_internal, nc);
             rc = rc ? rc : dalloc(c, &c->to_caller, nc);
+            rc = rc ? rc : dalloc(c, &c->cx, c->stride);
+            rc = rc ? rc : dalloc(c, &c->cy, c->stride);
             if (!rc) {
                 hipError_t e = hipSuccess;
                 if (e == hipSuccess) e = hipMemcpy(c->nbr, nb.data(), nb.size() * sizeof(int32_t), hipMemcpyHostToDevice);
@@ -575,6 +585,8 @@ int sme_init(sme_ctx **out, int level, const sme_mesh *mesh, const sme_params *p
                 if (e == hipSuccess) e = hipMemcpy(c->fw, fw.data(), fw.size() * sizeof(double), hipMemcpyHostToDevice);
                 if (e == hipSuccess) e = hipMemcpy(c->to_internal, inv.data(), nc * sizeof(int64_t), hipMemcpyHostToDevice);
                 if (e == hipSuccess) e = hipMemcpy(c->to_caller, order.data(), nc * sizeof(int64_t), hipMemcpyHostToDevice);
+                if (e == hipSuccess) e = hipMemcpy(c->cx, ccx.data(), ccx.size() * sizeof(double), hipMemcpyHostToDevice);
+                if (e == hipSuccess) e = hipMemcpy(c->cy, ccy.data(), ccy.size() * sizeof(double), hipMemcpyHostToDevice);
                 if (e != hipSuccess) rc = fail(c, SME_EHIP, "geometry upload: %s", hipGetErrorString(e));
             }
         }
@@ -778,6 +790,41 @@ int sme_time(sme_ctx *c, double *t, int64_t *steps)
     return SME_OK;
 }
 
+int sme_interpolate_3d(sme_ctx *c, int nz, const double *zeta, double rho, double *out)
+{
+    if (!c || !zeta || !out || nz < 1 || nz > kLiftMaxLevels || !(rho > 0) || !std::isfinite(rho)) return SME_EINVAL;
+    if (!c->has_state) return fail(c, SME_EINVAL, "no state loaded");
+    LiftArgs a{};
+    for (int l = 0; l < nz; ++l) {
+        if (!(zeta[l] >= 0.0 && zeta[l] <= 1.0)) return fail(c, SME_EINVAL, "sigma level %d outside [0, 1]", l);
+        a.zeta[l] = zeta[l];
+    }
+    hipPointerAttribute_t at{};
+    if (hipPointerGetAttributes(&at, out) != hipSuccess || at.type != hipMemoryTypeDevice) {
+        (void)hipGetLastError();
+        return fail(c, SME_EINVAL, "output %p is not device memory", (void *)out);
+    }
+    a.q = c->q[c->cur];
+    a.b = c->b;
+    a.stride = c->stride;
+    a.ncells = c->ncells;
+    a.nx = (int)c->nx;
+    a.ny = (int)c->ny;
+    a.inv_dx = c->dx > 0 ? 1.0 / c->dx : 0.0;
+    a.inv_dy = c->dy > 0 ? 1.0 / c->dy : 0.0;
+    for (int s = 0; s < 4; ++s) a.bc[s] = c->bc[s];
+    a.nbr = c->nbr;
+    a.cx = c->cx;
+    a.cy = c->cy;
+    a.to_caller = c->to_caller;
+    a.nz = nz;
+    a.rho_g = rho * c->p.g;
+    a.out = out;
+    const int kind = c->kind == SME_MESH_1D ? 1 : (c->kind == SME_MESH_2D_STRUCT ? 2 : 3);
+    HIPCHK(c, launch_lift(c->level, kind, a, c->stream));
+    return SME_OK;
+}
+
 int sme_current(const sme_ctx *c) { return c ? c->cur : SME_EINVAL; }
 int sme_nfields(const sme_ctx *c) { return c ? c->nf : SME_EINVAL; }
 int64_t sme_ncells(const sme_ctx *c) { return c ? c->ncells : SME_EINVAL; }
@@ -943,6 +990,8 @@ void sme_destroy(sme_ctx *c)
     (void)hipFree(c->fnx);
     (void)hipFree(c->fny);
     (void)hipFree(c->fw);
+    (void)hipFree(c->cx);
+    (void)hipFree(c->cy);
     (void)hipFree(c->to_internal);
     (void)hipFree(c->to_caller);
     (void)hipFree(c->slots);

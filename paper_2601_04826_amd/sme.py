@@ -27,7 +27,7 @@ CLOSURE_PRECISIONS = {"fp32": 0, "fp16": 1}  # SME_CLOSURE_FP32, SME_CLOSURE_FP1
 
 EXPORTS = [
     "sme_layout", "sme_workspace_size", "sme_init", "sme_set_state", "sme_get_state", "sme_eigmax", "sme_step",
-    "sme_run", "sme_time", "sme_current", "sme_nfields", "sme_ncells", "sme_level", "sme_state_device",
+    "sme_run", "sme_time", "sme_interpolate_3d", "sme_current", "sme_nfields", "sme_ncells", "sme_level", "sme_state_device",
     "sme_field_stride", "sme_step_static",
     "sme_basis_tensors", "sme_strerror", "sme_last_error", "sme_destroy",
     "sme_batch_init", "sme_batch_set_state", "sme_batch_get_state", "sme_batch_run", "sme_batch_time",
@@ -77,6 +77,7 @@ def _load():
         "sme_run": (i, [vp, i64, d, P(d), P(i64)]),
         "sme_time": (i, [vp, P(d), P(i64)]),
         "sme_current": (i, [vp]),
+        "sme_interpolate_3d": (i, [vp, i, vp, d, vp]),
         "sme_nfields": (i, [vp]),
         "sme_ncells": (i64, [vp]),
         "sme_level": (i, [vp]),
@@ -346,6 +347,16 @@ class Solver:
     def state_device(self):
         """(pointer, field stride) of the current state in the internal order."""
         return _lib.sme_state_device(self.ctx), _lib.sme_field_stride(self.ctx)
+
+    def interpolate_3d(self, zeta, rho=1.0):
+        """3D lifting of the current state at sigma levels zeta: dict of z, u,
+        v, w, p as numpy arrays [len(zeta), ncells] (caller cell order)."""
+        z = np.ascontiguousarray(zeta, dtype=np.float64)
+        out = torch.empty((5, z.size, self.ncells), dtype=torch.float64, device=self.q_dev[0].device)
+        _check(_lib.sme_interpolate_3d(self.ctx, int(z.size), z.ctypes.data_as(ctypes.c_void_p), float(rho),
+                                       ctypes.c_void_p(out.data_ptr())), self.ctx)
+        o = out.cpu().numpy()
+        return dict(z=o[0], u=o[1], v=o[2], w=o[3], p=o[4])
 
     def current(self):
         """The bound buffer (torch tensor [nfields, field_stride]) holding the state."""
