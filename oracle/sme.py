@@ -43,6 +43,10 @@ def lib():
         _lib.oracle_lambda.restype = d
         _lib.oracle_source.argtypes = [p, p, p]
         _lib.oracle_friction_step.argtypes = [p, p, d, p]
+        _lib.oracle_rhs2.argtypes = [p, p, p]
+        _lib.oracle_step2.argtypes = [p, p, d, p]
+        _lib.oracle_run2.argtypes = [p, p, p, i64, d]
+        _lib.oracle_run2.restype = d
         _lib.oracle_step_cells.argtypes = [p, p, d, p, i64, p]
         _lib.oracle_predict_cells.argtypes = [p, p, d, p, i64, p]
         _lib.oracle_cfl_dt.argtypes = [p, p, p]
@@ -85,7 +89,12 @@ class Oracle:
     """SME oracle bound to one mesh, level and parameter set."""
 
     def __init__(self, level, mesh, b=None, g=9.81, c_slip=0.0, nu=0.0, cfl=0.45, quad_points=3,
-                 implicit_friction=0):
+                 implicit_friction=0, order=1):
+        if order not in (1, 2):
+            raise ValueError("order must be 1 or 2")
+        if order == 2 and mesh.maxf != 2 * mesh.dim:
+            raise ValueError("the second-order scheme needs a 1D or structured grid")
+        self.order = order
         self.level = level
         self.mesh = mesh
         self.dim = mesh.dim
@@ -105,7 +114,7 @@ class Oracle:
         self._keep["b"] = bb
         self.b = bb
         self.params = dict(g=g, c_slip=c_slip, nu=nu, cfl=cfl, quad_points=quad_points,
-                           implicit_friction=int(implicit_friction))
+                           implicit_friction=int(implicit_friction), order=order)
         k = self._keep
         self._o = _OMesh(level, mesh.dim, mesh.ncells, mesh.maxf,
                          _p(mesh.nbr), _p(mesh.nx), _p(mesh.ny), _p(mesh.flen), _p(mesh.vol),
@@ -164,6 +173,10 @@ class Oracle:
         Q = self._state(Q)
         if dt is None:
             dt = self.cfl_dt(Q)[0]
+        if self.order == 2:
+            out = np.empty_like(Q)
+            self._lib.oracle_step2(ctypes.byref(self._o), _p(Q), dt, _p(out))
+            return (out if cells is None else out[:, np.asarray(cells)]), dt
         if cells is None:
             out = np.empty_like(Q)
             self._lib.oracle_step_cells(ctypes.byref(self._o), _p(Q), dt, None, 0, _p(out))
@@ -172,6 +185,13 @@ class Oracle:
             out = np.empty((self.nf, idx.size))
             self._lib.oracle_step_cells(ctypes.byref(self._o), _p(Q), dt, _p(idx), idx.size, _p(out))
         return out, dt
+
+    def rhs2(self, Q):
+        """dQ/dt of the second-order hyperbolic operator."""
+        Q = self._state(Q)
+        out = np.empty_like(Q)
+        self._lib.oracle_rhs2(ctypes.byref(self._o), _p(Q), _p(out))
+        return out
 
     def predict(self, Q, dt):
         """Hyperbolic predictor Q* only (no friction)."""
@@ -184,7 +204,8 @@ class Oracle:
         """n_steps steps from Q; returns (Q_end, t_end)."""
         Q = self._state(Q).copy()
         work = np.empty_like(Q)
-        t = self._lib.oracle_run(ctypes.byref(self._o), _p(Q), _p(work), int(n_steps), float(dt_fixed))
+        run = self._lib.oracle_run2 if self.order == 2 else self._lib.oracle_run
+        t = run(ctypes.byref(self._o), _p(Q), _p(work), int(n_steps), float(dt_fixed))
         return Q, t
 
 

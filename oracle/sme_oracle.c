@@ -275,26 +275,15 @@ static void ghost(const omesh *o, const double *qi, double bi, int64_t code, dou
     }
 }
 
-/* Per-face contribution for cell i: |e| (Fhat + NC/2), accumulated into acc. */
-static void face_term(const omesh *o, const double *qi, double bi, const double *qj, double bj,
-                      double nx, double ny, double len, double *acc)
+/* Path-conservative NC fluctuation along the straight path from (qi, bi) to
+ * (qj, bj): nc = int_0^1 B(Phi(s)).n ds (Q_j - Q_i, b_j - b_i), Gauss-Legendre in s. */
+static void nc_path(const omesh *o, const double *qi, double bi, const double *qj, double bj, double nx, double ny,
+                    double *nc_)
 {
     int nf = nfields(o), nc = nf + 1;
-    double fi[OR_MAXF], fj[OR_MAXF];
-    oracle_flux(o, qi, nx, ny, fi);
-    oracle_flux(o, qj, nx, ny, fj);
-    double li = oracle_lambda(o, qi, nx, ny);
-    double lj = oracle_lambda(o, qj, nx, ny);
-    double s = li > lj ? li : lj;
-    double wi[OR_MAXF], wj[OR_MAXF];
-    for (int f = 0; f < nf; f++) { wi[f] = qi[f]; wj[f] = qj[f]; }
-    wi[0] += bi;            /* Rusanov viscosity acts on the free surface h + b */
-    wj[0] += bj;
-    /* path-conservative NC fluctuation: int_0^1 B(Phi(s)).n ds (Q_j - Q_i, b_j - b_i) */
     double dq[OR_MAXF + 1];
     for (int f = 0; f < nf; f++) dq[f] = qj[f] - qi[f];
     dq[nf] = bj - bi;
-    double nc_[OR_MAXF];
     for (int f = 0; f < nf; f++) nc_[f] = 0.0;
     double mat[OR_MAXF * (OR_MAXF + 1)];
     for (int g = 0; g < o->nquad; g++) {
@@ -307,6 +296,25 @@ static void face_term(const omesh *o, const double *qi, double bi, const double 
             nc_[r] += o->qw[g] * v;
         }
     }
+}
+
+/* Per-face contribution for cell i: |e| (Fhat + NC/2), accumulated into acc. */
+static void face_term(const omesh *o, const double *qi, double bi, const double *qj, double bj,
+                      double nx, double ny, double len, double *acc)
+{
+    int nf = nfields(o);
+    double fi[OR_MAXF], fj[OR_MAXF];
+    oracle_flux(o, qi, nx, ny, fi);
+    oracle_flux(o, qj, nx, ny, fj);
+    double li = oracle_lambda(o, qi, nx, ny);
+    double lj = oracle_lambda(o, qj, nx, ny);
+    double s = li > lj ? li : lj;
+    double wi[OR_MAXF], wj[OR_MAXF];
+    for (int f = 0; f < nf; f++) { wi[f] = qi[f]; wj[f] = qj[f]; }
+    wi[0] += bi;            /* Rusanov viscosity acts on the free surface h + b */
+    wj[0] += bj;
+    double nc_[OR_MAXF];
+    nc_path(o, qi, bi, qj, bj, nx, ny, nc_);
     for (int f = 0; f < nf; f++) {
         double fhat = 0.5 * (fi[f] + fj[f]) - 0.5 * s * (wj[f] - wi[f]);
         acc[f] += len * (fhat + 0.5 * nc_[f]);
@@ -404,6 +412,172 @@ double oracle_run(const omesh *o, double *Q, double *work, int64_t n_steps, doub
     for (int64_t s = 0; s < n_steps; s++) {
         double dt = dt_fixed > 0.0 ? dt_fixed : oracle_cfl_dt(o, Q, NULL);
         oracle_step_cells(o, Q, dt, NULL, 0, work);
+        memcpy(Q, work, sizeof(double) * (size_t)nf * (size_t)o->ncells);
+        t += dt;
+    }
+    return t;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Second-order scheme on 1D and structured grids (face slot s lies on axis
+ * s / 2, on its minus side for even s and its plus side for odd s).
+ *
+ * Reconstruction (compute_derivatives, Sec. 2.1.2, with a limiter): per cell
+ * and axis the variables v = (eta = h + b, q_1 .. q_{nf-1}, b) get the slope
+ * sigma = minmod(v_i - v_minus, v_plus - v_i) (per cell width; the neighbour
+ * across a boundary face is the ghost of the cell), and the face values are
+ * v_i -/+ sigma / 2, with h = eta - b.  Reconstructing the free surface keeps
+ * the lake at rest exact.  If a face depth would not be positive the cell
+ * keeps zero slopes (first order).
+ * Semi-discrete operator: for every face the Rusanov flux and half the path
+ * fluctuation between the two reconstructed face values (the cell's own and
+ * the neighbour's, or its ghost), plus per axis the fluctuation inside the
+ * cell along the straight path from its minus-face to its plus-face value
+ * (the in-cell term of path-conservative schemes of second order).
+ * Time: two-stage SSP Runge-Kutta (Heun) for the hyperbolic part, then the
+ * friction step of the splitting (Eq. (3d)) on the result.                */
+
+static double minmod(double a, double b)
+{
+    if (a * b <= 0.0) return 0.0;
+    return fabs(a) < fabs(b) ? a : b;
+}
+
+/* state (q, b) of cell i -> reconstruction variables v[0..nf] */
+static void to_recon(int nf, const double *q, double b, double *v)
+{
+    v[0] = q[0] + b;
+    for (int f = 1; f < nf; f++) v[f] = q[f];
+    v[nf] = b;
+}
+
+/* reconstruction variables -> (q, b) */
+static void from_recon(int nf, const double *v, double *q, double *b)
+{
+    q[0] = v[0] - v[nf];
+    for (int f = 1; f < nf; f++) q[f] = v[f];
+    *b = v[nf];
+}
+
+/* limited slopes sig[cell][axis][nf + 1] */
+static void recon_slopes(const omesh *o, const double *Q, double *sig)
+{
+    int nf = nfields(o), na = o->maxf / 2, nv = nf + 1;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < o->ncells; i++) {
+        double qi[OR_MAXF], bi, vi[OR_MAXF + 1];
+        load_cell(o, Q, i, qi, &bi);
+        to_recon(nf, qi, bi, vi);
+        double *si = sig + i * na * nv;
+        for (int a = 0; a < na; a++) {
+            double vn[2][OR_MAXF + 1];
+            for (int side = 0; side < 2; side++) {
+                int s = 2 * a + side;
+                int64_t code = o->nbr[i * o->maxf + s];
+                double qn[OR_MAXF], bn;
+                if (code >= 0)
+                    load_cell(o, Q, code, qn, &bn);
+                else
+                    ghost(o, qi, bi, code, o->fnx[i * o->maxf + s], o->fny[i * o->maxf + s], qn, &bn);
+                to_recon(nf, qn, bn, vn[side]);
+            }
+            for (int f = 0; f < nv; f++) si[a * nv + f] = minmod(vi[f] - vn[0][f], vn[1][f] - vi[f]);
+        }
+        /* positive face depths, else first order */
+        int ok = 1;
+        for (int a = 0; a < na; a++)
+            for (int side = 0; side < 2; side++) {
+                double sg = side ? 0.5 : -0.5;
+                double eta = vi[0] + sg * si[a * nv + 0], b = vi[nf] + sg * si[a * nv + nf];
+                if (!(eta - b > 0.0)) ok = 0;
+            }
+        if (!ok)
+            for (int f = 0; f < na * nv; f++) si[f] = 0.0;
+    }
+}
+
+/* reconstructed (q, b) of cell i at its face slot s */
+static void face_value(const omesh *o, const double *Q, const double *sig, int64_t i, int s, double *q, double *b)
+{
+    int nf = nfields(o), na = o->maxf / 2, nv = nf + 1;
+    double qi[OR_MAXF], bi, v[OR_MAXF + 1];
+    load_cell(o, Q, i, qi, &bi);
+    to_recon(nf, qi, bi, v);
+    const double *si = sig + (i * na + s / 2) * nv;
+    double sg = (s % 2) ? 0.5 : -0.5;
+    for (int f = 0; f < nv; f++) v[f] += sg * si[f];
+    from_recon(nf, v, q, b);
+}
+
+/* R = dQ/dt of the hyperbolic part at second order (all cells) */
+void oracle_rhs2(const omesh *o, const double *Q, double *R)
+{
+    int nf = nfields(o), na = o->maxf / 2;
+    double *sig = (double *)malloc(sizeof(double) * (size_t)o->ncells * na * (nf + 1));
+    recon_slopes(o, Q, sig);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < o->ncells; i++) {
+        double acc[OR_MAXF];
+        for (int f = 0; f < nf; f++) acc[f] = 0.0;
+        for (int s = 0; s < o->maxf; s++) {
+            int64_t code = o->nbr[i * o->maxf + s];
+            double nx = o->fnx[i * o->maxf + s], ny = o->fny[i * o->maxf + s];
+            double len = o->flen[i * o->maxf + s];
+            double qL[OR_MAXF], bL, qR[OR_MAXF], bR;
+            face_value(o, Q, sig, i, s, qL, &bL);
+            if (code >= 0)
+                face_value(o, Q, sig, code, s ^ 1, qR, &bR);   /* the neighbour's value on the same face */
+            else
+                ghost(o, qL, bL, code, nx, ny, qR, &bR);
+            face_term(o, qL, bL, qR, bR, nx, ny, len, acc);
+        }
+        for (int a = 0; a < na; a++) {
+            /* inside the cell, from the minus face to the plus face, normal +axis */
+            double qm[OR_MAXF], bm, qp[OR_MAXF], bp, ncc[OR_MAXF];
+            face_value(o, Q, sig, i, 2 * a, qm, &bm);
+            face_value(o, Q, sig, i, 2 * a + 1, qp, &bp);
+            double nx = o->fnx[i * o->maxf + 2 * a + 1], ny = o->fny[i * o->maxf + 2 * a + 1];
+            double len = o->flen[i * o->maxf + 2 * a + 1];
+            nc_path(o, qm, bm, qp, bp, nx, ny, ncc);
+            for (int f = 0; f < nf; f++) acc[f] += len * ncc[f];
+        }
+        for (int f = 0; f < nf; f++) R[(int64_t)f * o->ncells + i] = -acc[f] / o->vol[i];
+    }
+    free(sig);
+}
+
+/* One second-order step of the whole mesh: out = Q^{n+1}. */
+void oracle_step2(const omesh *o, const double *Q, double dt, double *out)
+{
+    int nf = nfields(o);
+    size_t n = (size_t)nf * (size_t)o->ncells;
+    double *R = (double *)malloc(sizeof(double) * n), *Q1 = (double *)malloc(sizeof(double) * n);
+    oracle_rhs2(o, Q, R);
+    for (size_t k = 0; k < n; k++) Q1[k] = Q[k] + dt * R[k];
+    oracle_rhs2(o, Q1, R);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < o->ncells; i++) {
+        double q2[OR_MAXF], qn[OR_MAXF];
+        for (int f = 0; f < nf; f++) {
+            size_t k = (size_t)f * o->ncells + i;
+            q2[f] = 0.5 * Q[k] + 0.5 * (Q1[k] + dt * R[k]);
+        }
+        oracle_friction_step(o, q2, dt, qn);
+        for (int f = 0; f < nf; f++) out[(size_t)f * o->ncells + i] = qn[f];
+    }
+    free(R);
+    free(Q1);
+}
+
+/* n_steps second-order steps (dt_fixed > 0, else the CFL step of each Q^n);
+ * Q in place, work holds one state; returns the simulated time. */
+double oracle_run2(const omesh *o, double *Q, double *work, int64_t n_steps, double dt_fixed)
+{
+    double t = 0.0;
+    int nf = nfields(o);
+    for (int64_t s = 0; s < n_steps; s++) {
+        double dt = dt_fixed > 0.0 ? dt_fixed : oracle_cfl_dt(o, Q, NULL);
+        oracle_step2(o, Q, dt, work);
         memcpy(Q, work, sizeof(double) * (size_t)nf * (size_t)o->ncells);
         t += dt;
     }
