@@ -80,7 +80,16 @@ typedef struct sme_ctx sme_ctx;
  * fluctuation; implicit_friction selects how the friction ODE of the
  * splitting (Eq. (3d)) is stepped: 0 forward Euler on the predicted state,
  * 1 backward Euler (the cell-local linear solve per moment block, stable for
- * any nu dt / h^2: the implicit source step of Sec. 2.1.2). */
+ * any nu dt / h^2: the implicit source step of Sec. 2.1.2); order 1 is the
+ * first-order scheme (forward Euler, cell values at the faces), order 2 the
+ * second-order one on 1D and structured grids (least-squares-type limited
+ * reconstruction, the compute_derivatives building block of Sec. 2.1.2:
+ * minmod slopes of h + b, the momenta and b, the path fluctuation between the
+ * reconstructed face values plus the one inside each cell, two-stage SSP
+ * Runge-Kutta, then the friction step; the state then stays in one of the two
+ * bound buffers, the other holds the first stage).  Order 2 is not available
+ * on triangles, in the ensemble, with a learned closure or in sme_step_static
+ * (SME_EINVAL). */
 typedef struct {
     double g;
     double c_slip;
@@ -88,6 +97,7 @@ typedef struct {
     double cfl;
     int quad_points;
     int implicit_friction;
+    int order;
 } sme_params;
 
 /* Mesh description; all arrays are host memory, copied during sme_init.
@@ -112,11 +122,13 @@ typedef struct {
  * binds; no context and no device work.  Any output pointer may be NULL. */
 int sme_layout(int level, const sme_mesh *mesh, int *nfields, int64_t *ncells, int64_t *field_stride);
 
-/* Bytes of device memory sme_init allocates for a (level, mesh) pair besides
- * the caller's state buffers: bathymetry, Gauss points, time-step slots and,
- * on triangles, neighbours, normals, centroids and the two cell permutations.  Attaching
- * a learned closure adds its network and rates buffers. */
-int sme_workspace_size(int level, const sme_mesh *mesh, size_t *bytes);
+/* Bytes of device memory sme_init allocates for a (level, mesh, params)
+ * triple besides the caller's state buffers: bathymetry, Gauss points,
+ * time-step slots, the limited slopes of the second-order scheme and, on
+ * triangles, neighbours, normals, centroids and the two cell permutations
+ * (params NULL: first order).  Attaching a learned closure adds its network
+ * and rates buffers. */
+int sme_workspace_size(int level, const sme_mesh *mesh, const sme_params *params, size_t *bytes);
 
 /* Create a solver for the SME of the given level (0..8) on the mesh
  * (the solver initialisation of Sec. 2.1.2: model, mesh and settings in, state

@@ -210,7 +210,8 @@ int sme_batch_init(sme_batch **out, int n, const int *levels, const sme_mesh *me
     if (!out || n < 1 || !levels || !meshes || !params) return SME_EINVAL;
     *out = nullptr;
     if (params->quad_points < 1 || params->quad_points > kMaxQuad || !(params->cfl > 0) || !(params->g > 0) ||
-        params->c_slip < 0 || params->nu < 0 || (params->implicit_friction != 0 && params->implicit_friction != 1))
+        params->c_slip < 0 || params->nu < 0 || (params->implicit_friction != 0 && params->implicit_friction != 1) ||
+        params->order != 1)
         return SME_EINVAL;
     for (int i = 0; i < n; ++i) {
         const sme_mesh &m = meshes[i];

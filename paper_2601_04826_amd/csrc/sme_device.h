@@ -227,30 +227,13 @@ __device__ __forceinline__ void path_weights(const Quad &q, double hL, double dh
     }
 }
 
-// Face fluxes: Fhat (Rusanov) and D (path-integrated NC fluctuation), frame
-// fields [h, a_0..a_N, t_0..t_N].
+// Path-integrated NC fluctuation D between the frame states L and R (only
+// their h, b, qa, qt are read), given dqa = R.qa - L.qa and dqt = R.qt - L.qt.
 template <int N, bool TAN>
-__device__ __forceinline__ void face_flux(const Side<N, TAN> &L, const Side<N, TAN> &R, double g,
-                                          const Quad &q, double *Fhat, double *D)
+__device__ __forceinline__ void nc_fluct(const Side<N, TAN> &L, const Side<N, TAN> &R, double g, const Quad &q,
+                                         const double *dqa, const double *dqt, double *D)
 {
     constexpr int n = N + 1;
-    const double hs = 0.5 * fmax(L.lam, R.lam);
-    // Rusanov on W = (h + b, qa, qt)
-    Fhat[0] = fma(0.5, L.qa[0] + R.qa[0], -hs * ((R.h + R.b) - (L.h + L.b)));
-    double dqa[n];
-#pragma unroll
-    for (int k = 0; k < n; ++k) {
-        dqa[k] = R.qa[k] - L.qa[k];
-        Fhat[1 + k] = fma(0.5, L.Fa[k] + R.Fa[k], -hs * dqa[k]);
-    }
-    double dqt[TAN ? n : 1];
-    if constexpr (TAN) {
-#pragma unroll
-        for (int k = 0; k < n; ++k) {
-            dqt[k] = R.qt[k] - L.qt[k];
-            Fhat[1 + n + k] = fma(0.5, L.Ft[k] + R.Ft[k], -hs * dqt[k]);
-        }
-    }
     // path averages of the velocities
     double c0, c1;
     path_weights(q, L.h, R.h - L.h, c0, c1);
@@ -277,6 +260,33 @@ __device__ __forceinline__ void face_flux(const Side<N, TAN> &L, const Side<N, T
         D[1 + k] = va;
         if constexpr (TAN) D[1 + n + k] = vt;
     });
+}
+
+// Face fluxes: Fhat (Rusanov) and D (path-integrated NC fluctuation), frame
+// fields [h, a_0..a_N, t_0..t_N].
+template <int N, bool TAN>
+__device__ __forceinline__ void face_flux(const Side<N, TAN> &L, const Side<N, TAN> &R, double g,
+                                          const Quad &q, double *Fhat, double *D)
+{
+    constexpr int n = N + 1;
+    const double hs = 0.5 * fmax(L.lam, R.lam);
+    // Rusanov on W = (h + b, qa, qt)
+    Fhat[0] = fma(0.5, L.qa[0] + R.qa[0], -hs * ((R.h + R.b) - (L.h + L.b)));
+    double dqa[n];
+#pragma unroll
+    for (int k = 0; k < n; ++k) {
+        dqa[k] = R.qa[k] - L.qa[k];
+        Fhat[1 + k] = fma(0.5, L.Fa[k] + R.Fa[k], -hs * dqa[k]);
+    }
+    double dqt[TAN ? n : 1];
+    if constexpr (TAN) {
+#pragma unroll
+        for (int k = 0; k < n; ++k) {
+            dqt[k] = R.qt[k] - L.qt[k];
+            Fhat[1 + n + k] = fma(0.5, L.Ft[k] + R.Ft[k], -hs * dqt[k]);
+        }
+    }
+    nc_fluct<N, TAN>(L, R, g, q, dqa, dqt, D);
 }
 
 // Friction source (Sec. 3.4: slip at the bed, Newtonian bulk), explicit Euler

@@ -73,6 +73,8 @@ struct StepArgs {
     Slot *slots;
     int sa, sb, sc;
     ErrWord *err;
+    // second-order scheme: limited slopes [axis][nv][stride] (null = first order)
+    const double *slopes;
     // learned closure (level 1 only; null = plain step)
     const ClosureModel *closure;
     const float *rates;       // float2 rates of (q_0, q_1) normal to x at [cell], normal to y at [stride + cell]
@@ -124,6 +126,11 @@ hipError_t launch_run_1d_lds(int level, const StepArgs &a, int nsteps, double *d
 hipError_t launch_step_2d(int level, const StepArgs &a, hipStream_t s);
 int step_2d_waves_per_simd(int level);  // resident waves per SIMD of the structured step kernel
 hipError_t launch_step_tri(int level, const StepArgs &a, hipStream_t s);
+// second-order step on 1D (dim 1) and structured (dim 2) grids: slopes of a.q
+// into `slopes`, then stage 1 (a.qn = a.q + dt L) or stage 2 (a.qn = a.qn / 2 +
+// (a.q + dt L(a.q)) / 2, friction, CFL ratio) of the two-stage Runge-Kutta step
+hipError_t launch_recon2(int level, int dim, const StepArgs &a, double *slopes, hipStream_t s);
+hipError_t launch_flux2(int level, int dim, int stage, const StepArgs &a, const double *slopes, hipStream_t s);
 hipError_t launch_eig(int dim, int kind, int level, const StepArgs &a, hipStream_t s);
 hipError_t launch_slots_reset(Slot *slots, ErrWord *err, int sa, hipStream_t s);  // err may be null
 // closure network training and samples (k_mlp.hip)

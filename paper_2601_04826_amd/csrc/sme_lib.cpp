@@ -77,6 +77,7 @@ struct sme_ctx {
     float *rates = nullptr;             // closure rates of the current state (2 or 4 per cell)
     int closure_mode = 0;               // ClosurePrecision of the attached network
     double *ckpt = nullptr;             // state at the start of a closure chunk (sme_closure_run)
+    double *slopes = nullptr;           // limited slopes of the second-order scheme
     double *t_host = nullptr;           // pinned: simulated time after the latest graph with an end time
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};  // completion of the last graphs of a run
     int cus = 256;                      // compute units of the device
@@ -349,6 +350,19 @@ hipError_t launch_one_step(sme_ctx *c, double dt_fixed, double t_end)
     a.dt_fixed = dt_fixed;
     a.t_end = t_end;
     hipError_t e = hipSuccess;
+    if (c->slopes) {
+        // second order: stage 1 into the other buffer, stage 2 back in place
+        const int dim = c->kind == SME_MESH_1D ? 1 : 2;
+        e = launch_recon2(c->level, dim, a, c->slopes, c->stream);
+        if (e == hipSuccess) e = launch_flux2(c->level, dim, 1, a, c->slopes, c->stream);
+        StepArgs a2 = a;
+        a2.q = a.qn;
+        a2.qn = const_cast<double *>(a.q);
+        if (e == hipSuccess) e = launch_recon2(c->level, dim, a2, c->slopes, c->stream);
+        if (e == hipSuccess) e = launch_flux2(c->level, dim, 2, a2, c->slopes, c->stream);
+        if (e == hipSuccess) c->sa = (c->sa + 1) % 3;
+        return e;
+    }
     if (c->closure) e = launch_closure_rates(a, c->kind == SME_MESH_1D ? 1 : 2, c->closure_mode, c->cus, c->stream);
     if (e != hipSuccess) return e;
     switch (c->kind) {
@@ -447,7 +461,7 @@ int sme_layout(int level, const sme_mesh *mesh, int *nfields, int64_t *ncells, i
     return SME_OK;
 }
 
-int sme_workspace_size(int level, const sme_mesh *mesh, size_t *bytes)
+int sme_workspace_size(int level, const sme_mesh *mesh, const sme_params *params, size_t *bytes)
 {
     int nf = 0;
     int64_t nc = 0;
@@ -457,6 +471,8 @@ int sme_workspace_size(int level, const sme_mesh *mesh, size_t *bytes)
     const size_t st = (size_t)stride_of(nc);
     size_t n = st * sizeof(double)                 // bathymetry (internal order)
                + 3 * sizeof(Slot) + sizeof(ErrWord) + 2 * kMaxQuad * sizeof(double);
+    if (params && params->order == 2)  // limited slopes of the second-order scheme
+        n += (size_t)(mesh->kind == SME_MESH_1D ? 1 : 2) * (nf + 1) * st * sizeof(double);
     if (mesh->kind == SME_MESH_2D_TRI)
         n += 3 * st * (sizeof(int32_t) + 3 * sizeof(double))  // neighbours, normals, |e|/|V|
              + 2 * st * sizeof(double)                        // centroids
@@ -475,8 +491,10 @@ int sme_init(sme_ctx **out, int level, const sme_mesh *mesh, const sme_params *p
     int r = check_mesh(mesh, level, &nf, &nc);
     if (r != SME_OK) return r;
     if (params->quad_points < 1 || params->quad_points > kMaxQuad || !(params->cfl > 0) || !(params->g > 0) ||
-        params->c_slip < 0 || params->nu < 0 || (params->implicit_friction != 0 && params->implicit_friction != 1))
+        params->c_slip < 0 || params->nu < 0 || (params->implicit_friction != 0 && params->implicit_friction != 1) ||
+        (params->order != 1 && params->order != 2))
         return SME_EINVAL;
+    if (params->order == 2 && mesh->kind == SME_MESH_2D_TRI) return SME_EINVAL;
     sme_ctx *c = new (std::nothrow) sme_ctx();
     if (!c) return SME_ENOMEM;
     c->level = level;
@@ -532,6 +550,8 @@ int sme_init(sme_ctx **out, int level, const sme_mesh *mesh, const sme_params *p
         rc = check_device_buffer(c, q_dev[k], (size_t)nf * c->stride * sizeof(double));
     }
     rc = rc ? rc : dalloc(c, &c->b, (size_t)c->stride);
+    if (params->order == 2)
+        rc = rc ? rc : dalloc(c, &c->slopes, (size_t)(mesh->kind == SME_MESH_1D ? 1 : 2) * (nf + 1) * c->stride);
     rc = rc ? rc : dalloc(c, &c->slots, 3);
     rc = rc ? rc : dalloc(c, &c->err, 1);
     rc = rc ? rc : dalloc(c, &c->quad_dev, 2 * kMaxQuad);
@@ -714,7 +734,7 @@ int sme_run(sme_ctx *c, int64_t n_steps, double t_end, double *t_out, int64_t *s
     // a small 1D grid without a closure: one workgroup takes the steps with the
     // state in LDS, up to kLdsRunSteps per launch (checking the clock between
     // launches when there is an end time)
-    if (c->kind == SME_MESH_1D && !c->closure && getenv("SME_NO_LDS_RUN") == nullptr &&
+    if (c->kind == SME_MESH_1D && !c->closure && !c->slopes && getenv("SME_NO_LDS_RUN") == nullptr &&
         (c->nx + 61) / 62 <= kLdsRunMaxWindows[c->level] &&
         run_1d_lds_bytes(c->level, (int)c->nx) + 1024 <= c->lds_optin) {
         while (left > 0) {
@@ -860,8 +880,8 @@ __attribute__((visibility("hidden"))) int sme_internal_attach(sme_ctx *c, const 
         drop_graphs(c);
         return SME_OK;
     }
-    if (c->level != 1 || c->kind == SME_MESH_2D_TRI)
-        return fail(c, SME_EINVAL, "the learned closure acts on level-1 1D and structured 2D grids");
+    if (c->level != 1 || c->kind == SME_MESH_2D_TRI || c->slopes)
+        return fail(c, SME_EINVAL, "the learned closure acts on level-1 1D and structured 2D grids, first order");
     if (!c->closure) {
         if (dalloc(c, &c->closure, 1)) return SME_ENOMEM;
     }
@@ -1001,6 +1021,7 @@ void sme_destroy(sme_ctx *c)
     (void)hipFree(c->oor);
     (void)hipFree(c->rates);
     (void)hipFree(c->ckpt);
+    (void)hipFree(c->slopes);
     if (c->t_host) (void)hipHostFree(c->t_host);
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);

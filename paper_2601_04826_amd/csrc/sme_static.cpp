@@ -103,7 +103,8 @@ extern "C" int sme_step_static(int level, const sme_mesh *mesh, const sme_params
     int r = sme_layout(level, mesh, &nf, &nc, nullptr);
     if (r) return r;
     if (params->quad_points < 1 || params->quad_points > kMaxQuad || !(params->cfl > 0) || !(params->g > 0) ||
-        params->c_slip < 0 || params->nu < 0 || (params->implicit_friction != 0 && params->implicit_friction != 1))
+        params->c_slip < 0 || params->nu < 0 || (params->implicit_friction != 0 && params->implicit_friction != 1) ||
+        params->order != 1)
         return SME_EINVAL;
     if (field_stride < nc || field_stride % 256 != 0 || !aligned256(q) || !aligned256(q_next) || !aligned256(b))
         return SME_EINVAL;

@@ -43,7 +43,8 @@ EXPORTS = [
 
 class sme_params(ctypes.Structure):
     _fields_ = [("g", ctypes.c_double), ("c_slip", ctypes.c_double), ("nu", ctypes.c_double),
-                ("cfl", ctypes.c_double), ("quad_points", ctypes.c_int), ("implicit_friction", ctypes.c_int)]
+                ("cfl", ctypes.c_double), ("quad_points", ctypes.c_int), ("implicit_friction", ctypes.c_int),
+                ("order", ctypes.c_int)]
 
 
 class sme_mesh(ctypes.Structure):
@@ -68,7 +69,7 @@ def _load():
     P = ctypes.POINTER
     sig = {
         "sme_layout": (i, [i, vp, P(i), P(i64), P(i64)]),
-        "sme_workspace_size": (i, [i, vp, P(ctypes.c_size_t)]),
+        "sme_workspace_size": (i, [i, vp, vp, P(ctypes.c_size_t)]),
         "sme_init": (i, [P(vp), i, vp, vp, P(vp), vp, i, vp]),
         "sme_set_state": (i, [vp, vp, i]),
         "sme_get_state": (i, [vp, vp, i]),
@@ -149,8 +150,8 @@ def _ptr(a):
     return a.ctypes.data_as(ctypes.c_void_p), False
 
 
-def make_params(g=9.81, c_slip=0.0, nu=0.0, cfl=0.45, quad_points=3, implicit_friction=0):
-    return sme_params(g, c_slip, nu, cfl, quad_points, int(implicit_friction))
+def make_params(g=9.81, c_slip=0.0, nu=0.0, cfl=0.45, quad_points=3, implicit_friction=0, order=1):
+    return sme_params(g, c_slip, nu, cfl, quad_points, int(implicit_friction), int(order))
 
 
 def make_mesh(problem):
@@ -186,9 +187,10 @@ def sme_layout(level, mesh):
     return nf.value, nc.value, st.value
 
 
-def sme_workspace_size(level, mesh):
+def sme_workspace_size(level, mesh, params=None):
     n = ctypes.c_size_t()
-    _check(_lib.sme_workspace_size(level, ctypes.byref(mesh), ctypes.byref(n)))
+    _check(_lib.sme_workspace_size(level, ctypes.byref(mesh), ctypes.byref(params) if params is not None else None,
+                                   ctypes.byref(n)))
     return n.value
 
 

@@ -33,7 +33,7 @@ nu = 0.1 m^2/s, CFL 0.45, 3 Gauss points on the path integral.
 """
 import numpy as np
 
-DEFAULT_PARAMS = dict(g=9.81, c_slip=1.0, nu=0.1, cfl=0.45, quad_points=3, implicit_friction=0)
+DEFAULT_PARAMS = dict(g=9.81, c_slip=1.0, nu=0.1, cfl=0.45, quad_points=3, implicit_friction=0, order=1)
 
 
 def nfields(level, dim):

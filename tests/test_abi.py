@@ -90,6 +90,9 @@ def test_workspace_size(sme):
     t, _ = sme.make_mesh(dict(kind="tri", vert=vert, tri=np.array([[0, 1, 2], [1, 3, 2]], dtype=np.int32)))
     wt = sme.sme_workspace_size(3, t)
     assert wt >= 256 * 8 + 3 * 256 * (4 + 24) + 2 * 2 * 8
+    # the second-order scheme adds the slopes of 2 axes x (nfields + 1) variables
+    w2 = sme.sme_workspace_size(2, m, sme.make_params(order=2))
+    assert w2 - ws == 2 * 8 * st * 8
 
 
 def test_strerror(sme):

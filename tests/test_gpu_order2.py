@@ -1,0 +1,156 @@
+"""GPU parity of the second-order scheme (sme_params.order = 2) with the oracle.
+
+Both sides reconstruct with the same minmod slopes of (h + b, momenta, b),
+evaluate the Rusanov flux and path fluctuation between reconstructed face
+values plus the in-cell fluctuation, and take two SSP Runge-Kutta stages
+before the friction step; they differ only in rounding order (the GPU works in
+the face frame with compile-time tensors, the oracle with dense loops).
+Metric per field: max |gpu - oracle| / max |oracle| <= 1e-10.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import sme as orc
+from paper_2601_04826_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+O2 = dict(order=2)
+
+
+@pytest.fixture(scope="module")
+def sme():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2601_04826_amd import sme as m
+
+    return m
+
+
+def rel_linf(gpu, ref):
+    worst = 0.0
+    for f in range(ref.shape[0]):
+        scale = np.max(np.abs(ref[f]))
+        if scale == 0.0:
+            assert np.all(gpu[f] == 0.0), f"field {f} must be exactly zero"
+            continue
+        worst = max(worst, np.max(np.abs(gpu[f] - ref[f])) / scale)
+    return worst
+
+
+def run_both(sme, p, steps, **over):
+    print(f"case {p['kind']} level {p['level']} cells {p['ncells']} steps {steps} {over}", flush=True)
+    sys.stdout.flush()
+    s = sme.Solver(p, **over)
+    s.set_state(p["q"])
+    cur0 = sme.lib().sme_current(s.ctx)
+    t_gpu, n_gpu = s.run(steps)
+    assert sme.lib().sme_current(s.ctx) == cur0      # the second-order state stays in its buffer
+    q_gpu = s.get_state()
+    s.close()
+    o = orc.from_problem(p, **over)
+    q_orc, t_orc = o.run(p["q"], steps)
+    assert n_gpu == steps
+    return q_gpu, q_orc, t_gpu, t_orc
+
+
+def with_moments(p, seed, amp=0.3):
+    p = dict(p)
+    q = p["q"].copy()
+    q[1:] = q[0] * np.random.default_rng(seed).uniform(-amp, amp, size=q[1:].shape)
+    p["q"] = q
+    return p
+
+
+@pytest.mark.parametrize("level", range(0, 9))
+def test_order2_levels_1d(sme, level):
+    for bc in (("extrap", "wall"), ("periodic", "periodic")):
+        p = with_moments(W.dam_break_1d(n=150, level=level, bc=bc), level)
+        p["b"] = 0.05 * np.random.default_rng(level).uniform(size=150)
+        q_gpu, q_orc, t_gpu, t_orc = run_both(sme, p, 80, **O2)
+        assert rel_linf(q_gpu, q_orc) <= 1e-10, bc
+        assert abs(t_gpu - t_orc) <= 1e-12 * t_orc
+
+
+@pytest.mark.parametrize("level", [0, 1, 2, 3, 4, 8])
+def test_order2_levels_2d(sme, level):
+    for bc in (("wall", "wall", "periodic", "periodic"), ("periodic", "periodic", "extrap", "wall")):
+        p = with_moments(W.struct_2d(n=45, level=level, L=4.5, bc=bc), 20 + level)
+        q_gpu, q_orc, t_gpu, t_orc = run_both(sme, p, 40, **O2)
+        assert rel_linf(q_gpu, q_orc) <= 1e-10, bc
+        assert abs(t_gpu - t_orc) <= 1e-12 * t_orc
+
+
+def test_order2_struct_128_1000_steps(sme):
+    p = W.struct_2d(n=128, level=2)
+    q_gpu, q_orc, t_gpu, t_orc = run_both(sme, p, 1000, **O2)
+    assert rel_linf(q_gpu, q_orc) <= 1e-10
+    assert abs(t_gpu - t_orc) <= 1e-11 * t_orc
+    m0 = math.fsum(p["q"][0])
+    assert abs(math.fsum(q_gpu[0]) - m0) / m0 <= 1e-13
+
+
+def test_order2_dam_break_1d_full(sme):
+    p = W.dam_break_1d()
+    q_gpu, q_orc, t_gpu, t_orc = run_both(sme, p, 1000, **O2)
+    assert rel_linf(q_gpu, q_orc) <= 1e-10
+    assert abs(t_gpu - t_orc) <= 1e-12 * t_orc
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (2, 3), (70, 1), (1, 9), (63, 2)])
+def test_order2_degenerate_grids(sme, shape):
+    nx, ny = shape
+    rng = np.random.default_rng(nx * 7 + ny)
+    q = W.random_state_2d(2, nx * ny, seed=4)
+    for bc in ("periodic", "wall", "extrap"):
+        p = W._problem("2d", 2, nx * ny, q, rng.uniform(0, 0.05, nx * ny), 30, nx=nx, ny=ny, x0=0.0,
+                       x1=nx / 10.0, y0=0.0, y1=ny / 10.0, bc=(bc,) * 4)
+        q_gpu, q_orc, t_gpu, t_orc = run_both(sme, p, 30, **O2)
+        scale = np.maximum(np.abs(q_orc).max(axis=1), np.abs(p["q"]).max(axis=1))
+        assert np.max(np.abs(q_gpu - q_orc).max(axis=1) / scale) <= 1e-10, bc
+
+
+def test_order2_implicit_friction(sme):
+    p = with_moments(W.struct_2d(n=50, level=3, L=5.0), 7)
+    over = dict(order=2, implicit_friction=1, nu=2.0)
+    q_gpu, q_orc, _, _ = run_both(sme, p, 50, **over)
+    scale = np.maximum(np.abs(q_orc).max(axis=1), np.abs(p["q"]).max(axis=1))
+    assert np.max(np.abs(q_gpu - q_orc).max(axis=1) / scale) <= 1e-10
+
+
+def test_order2_lake_at_rest_and_end_time(sme):
+    p = W.struct_2d(n=64, level=2, steps=0)
+    q = np.zeros_like(p["q"])
+    q[0] = 1.5 - p["b"]
+    p["q"] = q
+    s = sme.Solver(p, order=2)
+    s.set_state(q)
+    t, n = s.run(10 ** 6, t_end=0.05)
+    out = s.get_state()
+    s.close()
+    assert t == pytest.approx(0.05, rel=1e-14)
+    assert np.max(np.abs(out[1:])) <= 1e-12 and np.max(np.abs(out[0] - q[0])) <= 1e-12
+
+
+def test_order2_deterministic_and_rejected_where_unsupported(sme):
+    p = with_moments(W.struct_2d(n=90, level=2), 3)
+    outs = []
+    for _ in range(2):
+        s = sme.Solver(p, order=2)
+        s.set_state(p["q"])
+        s.run(37)
+        outs.append(s.get_state())
+        s.close()
+    assert np.array_equal(outs[0], outs[1])
+    vert, tri = W.delaunay_unit_square(50, seed=1)
+    pt = dict(kind="tri", level=1, ncells=len(tri), q=W.random_state_2d(1, len(tri), 0), b=None, steps=1,
+              vert=vert, tri=tri, params=dict(W.DEFAULT_PARAMS))
+    with pytest.raises(sme.SmeError):
+        sme.Solver(pt, order=2)
+    with pytest.raises(sme.SmeError):
+        sme.Batch([W.struct_2d(n=40, level=1)], order=2)
