@@ -247,10 +247,15 @@ __device__ __forceinline__ void x_faces(const StepArgs &a, const Cell2<N> &C, do
     }
 }
 
-// predictor, friction, store, CFL ratio of the new state
+// predictor, friction, store, CFL ratio of the new state.  The cell is
+// column col of the row starting at element rowoff (a wave-uniform value, so
+// the stores address memory as a uniform base plus a 32-bit lane offset and
+// no 64-bit per-lane address is held); step1 is the index of this step for
+// the non-physical-state word (read once per band: a load of the slot here
+// would make every row wait for its stores before reusing the register).
 template <int N, bool CLOS, bool IMP>
-__device__ __forceinline__ double finish_cell(const StepArgs &a, double dt, int64_t cell, bool out,
-                                              const Cell2<N> &c, const double *acc)
+__device__ __forceinline__ double finish_cell(const StepArgs &a, double dt, int64_t rowoff, int col, bool out,
+                                              const Cell2<N> &c, const double *acc, long long step1)
 {
     constexpr int n = N + 1;
     const double h = fma(-dt, acc[0], c.h);
@@ -262,11 +267,13 @@ __device__ __forceinline__ double finish_cell(const StepArgs &a, double dt, int6
     }
     const double ih = rcp(h);
     friction_step<N, true, IMP>(qx, qy, ih, dt, a.c_slip, a.nu);
+    const unsigned uc = (unsigned)col;
     if constexpr (CLOS) {
         // learned closure: rates of (q_0, q_1) normal to x and to y from the rates pass
         if (out) {
-            const float2 rx = reinterpret_cast<const float2 *>(a.rates)[cell];
-            const float2 ry = reinterpret_cast<const float2 *>(a.rates)[a.stride + cell];
+            const float2 *rr = reinterpret_cast<const float2 *>(a.rates) + rowoff;
+            const float2 rx = rr[uc];
+            const float2 ry = (rr + a.stride)[uc];
             qx[0] = fma(dt, (double)rx.x, qx[0]);
             qx[1] = fma(dt, (double)rx.y, qx[1]);
             qy[0] = fma(dt, (double)ry.x, qy[0]);
@@ -275,15 +282,16 @@ __device__ __forceinline__ double finish_cell(const StepArgs &a, double dt, int6
     }
     double r = 0.0;
     if (out) {
-        a.qn[cell] = h;
+        double *const base = a.qn + rowoff;
+        base[uc] = h;
         double sum = h;
 #pragma unroll
         for (int k = 0; k < n; ++k) {
-            a.qn[(1 + k) * a.stride + cell] = qx[k];
-            a.qn[(1 + n + k) * a.stride + cell] = qy[k];
+            (base + (int64_t)(1 + k) * a.stride)[uc] = qx[k];
+            (base + (int64_t)(1 + n + k) * a.stride)[uc] = qy[k];
             sum += qx[k] + qy[k];
         }
-        flag_bad(a, !(h > 0.0) || !isfinite(sum));
+        flag_bad_at(a, !(h > 0.0) || !isfinite(sum), step1);
         double lm;
         r = cfl_ratio_2d<N>(a.g, h, ih, qx, qy, a.idx, a.idy, &lm);
         if (!(r >= 0.0)) r = 0.0;
@@ -296,11 +304,12 @@ __device__ __forceinline__ double finish_cell(const StepArgs &a, double dt, int6
 template <int N, bool CLOS, bool IMP>
 __device__ __forceinline__ void row(const StepArgs &a, double dt, Cell2<N> &P, double *accP, Cell2<N> &C,
                                     double *accC, const Raw2<N> &raw, int j, int c, bool outc, bool finish_p,
-                                    double &rmax)
+                                    double &rmax, long long step1)
 {
     cell_flux<N>(C, raw, a.g);
     y_face<N, true>(a, P, C, accP, accC, finish_p);
-    if (finish_p) rmax = fmax(rmax, finish_cell<N, CLOS, IMP>(a, dt, (int64_t)(j - 1) * a.nx + c, outc, P, accP));
+    if (finish_p)
+        rmax = fmax(rmax, finish_cell<N, CLOS, IMP>(a, dt, (int64_t)(j - 1) * a.nx, c, outc, P, accP, step1));
     x_faces<N>(a, C, accC);
 }
 
@@ -308,11 +317,11 @@ __device__ __forceinline__ void row(const StepArgs &a, double dt, Cell2<N> &P, d
 template <int N, bool CLOS, bool IMP>
 __device__ __forceinline__ void close_band(const StepArgs &a, double dt, Cell2<N> &P, double *accP,
                                            Cell2<N> &G, const Raw2<N> &raw, int j1, int c, bool outc,
-                                           double &rmax)
+                                           double &rmax, long long step1)
 {
     cell_flux<N>(G, raw, a.g);
     y_face<N, false>(a, P, G, accP, nullptr, true);
-    rmax = fmax(rmax, finish_cell<N, CLOS, IMP>(a, dt, (int64_t)(j1 - 1) * a.nx + c, outc, P, accP));
+    rmax = fmax(rmax, finish_cell<N, CLOS, IMP>(a, dt, (int64_t)(j1 - 1) * a.nx, c, outc, P, accP, step1));
 }
 
 // Whole band (strip sx, band sy) of one grid: returns the largest CFL ratio
@@ -332,6 +341,10 @@ __device__ __forceinline__ double band2d(const StepArgs &a, double dt, int sx, i
     (void)ghost_index(c, a.nx, a.bc[0], a.bc[1], mx);
     const bool outc = lane >= 1 && lane <= kOut && c < a.nx;
     double rmax = 0.0;
+    // index of this step for the non-physical-state word, wave-uniform
+    const long long st = a.slots[a.sa].step + 1;
+    const long long step1 = (long long)(((unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane((int)(st >> 32)) << 32) |
+                                        (unsigned)__builtin_amdgcn_readfirstlane((int)st));
     Cell2<N> A, B;
     double accA[nf], accB[nf];
 #pragma unroll
@@ -350,20 +363,20 @@ __device__ __forceinline__ double band2d(const StepArgs &a, double dt, int sx, i
         // buf0's previous row was read into registers before its arithmetic
         read_row<N>(a, j, mx, buf1, cur);
         stage_row<N>(a, j + 1, voff, buf0);  // next row, or the closing halo row
-        row<N, CLOS, IMP>(a, dt, A, accA, B, accB, cur, j, c, outc, j > j0, rmax);
+        row<N, CLOS, IMP>(a, dt, A, accA, B, accB, cur, j, c, outc, j > j0, rmax, step1);
         wait_staged();
         if (++j == j1) {
             read_row<N>(a, j1, mx, buf0, cur);
-            close_band<N, CLOS, IMP>(a, dt, B, accB, A, cur, j1, c, outc, rmax);
+            close_band<N, CLOS, IMP>(a, dt, B, accB, A, cur, j1, c, outc, rmax, step1);
             break;
         }
         read_row<N>(a, j, mx, buf0, cur);
         stage_row<N>(a, j + 1, voff, buf1);
-        row<N, CLOS, IMP>(a, dt, B, accB, A, accA, cur, j, c, outc, true, rmax);
+        row<N, CLOS, IMP>(a, dt, B, accB, A, accA, cur, j, c, outc, true, rmax, step1);
         wait_staged();
         if (++j == j1) {
             read_row<N>(a, j1, mx, buf1, cur);
-            close_band<N, CLOS, IMP>(a, dt, A, accA, B, cur, j1, c, outc, rmax);
+            close_band<N, CLOS, IMP>(a, dt, A, accA, B, cur, j1, c, outc, rmax, step1);
             break;
         }
     }
