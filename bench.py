@@ -26,6 +26,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# the headline metric: cell-updates/s of the structured step (with its HBM
+# roofline fraction) and, in the same line, the closure's speedup over level 8
+METRIC = "SME cell-updates/s (FP64, % HBM peak); closure vs level-8 speedup at equal L1 error"
 FP64_PEAK_TFS = 78.6  # MI355X FP64 vector peak
 
 # Algorithmic bytes per cell-update of the step kernel: read every field of
@@ -124,6 +127,8 @@ def main():
     ap.add_argument("--closure-seeds", type=int, default=64, help="closure: level-8 training runs")
     ap.add_argument("--closure-steps", type=int, default=1000, help="closure: steps per training run")
     ap.add_argument("--closure-epochs", type=int, default=15)
+    ap.add_argument("--closure-ref-steps", type=int, default=200, help="closure: level-8 steps fixing the end time")
+    ap.add_argument("--no-closure", action="store_true", help="default workload: skip the closure comparison")
     ap.add_argument("--closure-precision", default="fp16", choices=["fp16", "fp32"],
                     help="closure: network evaluation whose throughput is the headline value")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -204,7 +209,7 @@ def main():
     achieved = alg_bytes / per_launch_s / 1e9
     traffic = load_traffic(args.workload, alg_bytes)
     out = {
-        "metric": "SME cell-updates/s (FP64)",
+        "metric": METRIC,
         "value": value,
         "unit": "cell-updates/s",
         "n_gpus": 1,
@@ -234,6 +239,13 @@ def main():
                                    "source": "executed FP64 flops per launch from rocprofv3 counters"}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(problem, args.cpu_seconds)
+    if args.workload == "struct_2d_1024_l2" and not args.no_closure:
+        # the second half of the headline metric: level 1 + closure against
+        # level 8 at the same simulated time (2048^2 periodic grid)
+        cmp_, mlp = closure_comparison(args, torch, sme, workloads,
+                                       lambda m: print(m, file=sys.stderr, flush=True))
+        mlp.close()
+        out["closure"] = cmp_
     print(json.dumps(out), flush=True)
 
 
@@ -257,11 +269,17 @@ def _rel_l1(q, ref):
     return [float((q[f] - ref[f]).abs().sum() / ref[f].abs().sum()) for f in (0, 1)]
 
 
-def bench_closure(args, wl, torch, sme, workloads):
-    """Learned closure: train on level-8 runs the solver generates, then run
-    level 1 + closure and plain level 8 (and plain level 1) on a 2048^2 periodic
-    2D grid to the same time; report both throughputs, the speedup at the same
-    simulated time and the relative L1 errors of (h, hu) against level 8."""
+def closure_comparison(args, torch, sme, workloads, log):
+    """Learned closure against the plain hierarchy on a 2048^2 periodic 2D grid.
+
+    Trains the network on level-8 1D runs the solver generates (library
+    kernels: sample extraction, sme_closure_train), runs plain level 8 for
+    args.closure_ref_steps steps to fix the end time T, then level 1 + closure
+    through the fallback policy (ClosureSolver: chunks with device
+    checkpoints, level 8 from the lifted state if the features leave the
+    training box), plain level 1, and plain levels 2, 3, ... until one reaches
+    the closure's error.  Returns a dict of wall times (synchronised, same T),
+    speedups and relative L1 errors of (h, hu) against level 8."""
     from paper_2601_04826_amd import closure
 
     st = torch.cuda.Stream()
@@ -274,90 +292,93 @@ def bench_closure(args, wl, torch, sme, workloads):
     mlp, sc, hist = closure.fit(feat, targ, epochs=args.closure_epochs, batch=4096, lr=3e-3, lr_end=1e-4,
                                 stream=st)
     t2 = time.perf_counter()
-    print(f"[bench] closure data: {feat.shape[0]} samples from {args.closure_seeds} level-8 runs in {t1 - t0:.1f} s; "
-          f"training {args.closure_epochs} epochs in {t2 - t1:.1f} s (loss {hist[0]:.4f} -> {hist[-1]:.4f})",
-          file=sys.stderr, flush=True)
+    log(f"[bench] closure data: {feat.shape[0]} samples from {args.closure_seeds} level-8 runs in {t1 - t0:.1f} s; "
+        f"training {args.closure_epochs} epochs in {t2 - t1:.1f} s (loss {hist[0]:.4f} -> {hist[-1]:.4f})")
     p8 = workloads.smooth_2d(n=2048, level=8, seed=2000)
     cells = p8["ncells"]
 
-    def timed(solver, n_steps, t_end):
-        solver.run(2, t_end=0.0)  # warm-up (then reset below)
-        return None
+    def wall(fn):
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - w0) * 1e3
 
-    # level 8 reference: args.steps steps fix the end time
+    # level 8 reference: a fixed number of steps fixes the end time T
     s8 = sme.Solver(p8, stream=st.cuda_stream)
     q8_init = torch.from_numpy(p8["q"]).cuda()  # initial states from device memory
     torch.cuda.synchronize()
     s8.set_state(q8_init)
     s8.run(3)
     s8.set_state(q8_init)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(st)
-    s8.run(args.steps, sync=False)
-    e1.record(st)
-    torch.cuda.synchronize()
-    ms8 = e0.elapsed_time(e1)
+    ms8 = wall(lambda: s8.run(args.closure_ref_steps))
     T, n8 = s8.time()
     ref = _state_hhu(torch, s8)
     s8.close()
     del q8_init
-    q1_init = torch.from_numpy(closure._project_state(p8["q"], p8)).cuda()
+    q8_dev = torch.from_numpy(p8["q"]).cuda()
     torch.cuda.synchronize()
-    results = {}
-    for name, net, prec in (("closure_fp16", mlp, "fp16"), ("closure_fp32", mlp, "fp32"), ("plain", None, None)):
-        p1 = dict(p8, level=1, q=q1_init)
-        s1 = sme.Solver(p1, stream=st.cuda_stream)
-        if net is not None:
-            s1.attach_closure(net, precision=prec)
-        s1.set_state(q1_init)
-        s1.run(3)
-        s1.set_state(q1_init)
-        torch.cuda.synchronize()
-        e0.record(st)
-        s1.run(100 * args.steps, t_end=T, sync=False)
-        e1.record(st)
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1)
-        t1_, n1 = s1.time()
-        q1 = _state_hhu(torch, s1)
-        oor = s1.out_of_range() if net is not None else 0
-        s1.close()
-        err = _rel_l1(q1, ref)
-        results[name] = dict(ms=ms, steps=n1, t=t1_, err_h=err[0], err_hu=err[1], out_of_range=oor)
-    # equal-error comparison: the smallest plain level whose error is within
-    # the closure's, and the closure's speedup over it at the same end time
-    tgt = results["closure_" + args.closure_precision]
-    equal = None
-    for lev in range(2, 8):
-        pN = workloads.smooth_2d(n=2048, level=8, seed=2000)
-        qN = torch.from_numpy(_project_level(pN["q"], pN, lev)).cuda()
-        pN = dict(pN, level=lev, q=None)
+    res = {}
+    # level 1 + closure through the fallback policy (the projection of the
+    # level-8 initial state is taken on the device)
+    cs = closure.ClosureSolver(p8, mlp, chunk=50, stream=st.cuda_stream, precision=args.closure_precision)
+    cs.set_state(q8_dev)
+    cs.run_to(T / 50, lifted=False)  # warm-up (graphs, kernels)
+    cs.set_state(q8_dev)
+    ms = wall(lambda: cs.run_to(T, lifted=False))
+    q1 = _state_hhu(torch, cs.final_solver())
+    err = _rel_l1(q1, ref)
+    res["closure"] = dict(ms=ms, steps=cs.steps, t=cs.t, err_h=err[0], err_hu=err[1],
+                          fell_back_at=cs.fell_back_at, out_of_range_cell_steps=cs.s1.out_of_range(),
+                          precision=args.closure_precision)
+    cs.close()
+
+    def plain(lev):
+        pN = dict(p8, level=lev, q=None)
+        qN = torch.from_numpy(_project_level(p8["q"], p8, lev)).cuda()
         sN = sme.Solver(pN, stream=st.cuda_stream)
         sN.set_state(qN)
         sN.run(3)
         sN.set_state(qN)
-        torch.cuda.synchronize()
-        e0.record(st)
-        sN.run(100 * args.steps, t_end=T, sync=False)
-        e1.record(st)
-        torch.cuda.synchronize()
-        msN = e0.elapsed_time(e1)
-        qNf = _state_hhu(torch, sN)
+        msN = wall(lambda: sN.run(100 * args.closure_ref_steps, t_end=T))
+        tN, nN = sN.time()
+        e = _rel_l1(_state_hhu(torch, sN), ref)
         sN.close()
-        errN = _rel_l1(qNf, ref)
-        print(f"[bench] plain level {lev}: {msN:.1f} ms, err_h {errN[0]:.3e}, err_hu {errN[1]:.3e}",
-              file=sys.stderr, flush=True)
-        if errN[0] + errN[1] <= tgt["err_h"] + tgt["err_hu"]:
-            equal = dict(level=lev, ms=msN, err_h=errN[0], err_hu=errN[1], speedup_closure_over_it=msN / tgt["ms"])
+        return dict(level=lev, ms=msN, steps=nN, t=tN, err_h=e[0], err_hu=e[1])
+
+    res["plain_level1"] = plain(1)
+    c, pl = res["closure"], res["plain_level1"]
+    ce = c["err_h"] + c["err_hu"]
+    equal = None
+    for lev in range(2, 8):
+        r = plain(lev)
+        log(f"[bench] plain level {lev}: {r['ms']:.1f} ms, err_h {r['err_h']:.3e}, err_hu {r['err_hu']:.3e}")
+        if r["err_h"] + r["err_hu"] <= ce:
+            equal = dict(r, speedup_closure_over_it=r["ms"] / c["ms"])
             break
-    pl = results["plain"]
-    for r in results.values():
-        r["speedup_vs_level8_same_time"] = ms8 / r["ms"]
-        r["error_ratio_over_plain_level1"] = (r["err_h"] + r["err_hu"]) / (pl["err_h"] + pl["err_hu"])
-    c = results["closure_" + args.closure_precision]
+    out = {
+        "grid": "2048x2048 periodic smooth 2D, level-8 reference", "t_end": T, "cells": cells,
+        "training": f"{args.closure_seeds} level-8 1D runs x {args.closure_steps} steps, {feat.shape[0]} samples, "
+                    f"{args.closure_epochs} epochs",
+        "level8": dict(ms=ms8, steps=n8, cell_updates_per_s=cells * n8 / (ms8 * 1e-3)),
+        "closure": c, "plain_level1": pl,
+        "speedup_vs_level8": ms8 / c["ms"],
+        "error_ratio_over_plain_level1": ce / (pl["err_h"] + pl["err_hu"]),
+        "within_error_budget": ce <= 2.0 * (pl["err_h"] + pl["err_hu"]),
+        "smallest_plain_level_at_closure_error": equal,
+        "timing": "wall clock between device synchronisations, same simulated end time",
+    }
+    return out, mlp
+
+
+def bench_closure(args, wl, torch, sme, workloads):
+    """The closure workload: the comparison above, with the closure's
+    throughput as the headline value."""
+    cmp_, mlp = closure_comparison(args, torch, sme, workloads,
+                                   lambda m: print(m, file=sys.stderr, flush=True))
+    c = cmp_["closure"]
+    cells = cmp_["cells"]
     value = cells * c["steps"] / (c["ms"] * 1e-3)
-    alg = bytes_per_cell("2d", 1) * cells
     # network work per cell and step: two directions x (9x64 + 64x64 + 64x2) multiply-adds
     flops = 2 * 2 * (9 * 64 + 64 * 64 + 64 * 2) * cells * c["steps"]
     fp16 = args.closure_precision == "fp16"
@@ -369,20 +390,18 @@ def bench_closure(args, wl, torch, sme, workloads):
         "unit": "cell-updates/s", "n_gpus": 1, "steps": c["steps"], "warmup": 3,
         "ms_per_step": c["ms"] / c["steps"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64+f16mfma" if fp16 else "f64+f32", "data": "synthetic",
-        "config": {"workload": wl["name"], "cells": cells, "t_end": T, "level8_steps": n8,
-                   "training": f"{args.closure_seeds} level-8 1D runs x {args.closure_steps} steps, "
-                               f"{feat.shape[0]} samples, {args.closure_epochs} epochs"},
+        "config": {"workload": wl["name"], "cells": cells, "t_end": cmp_["t_end"]},
         "roofline": {"bound": "mfma" if fp16 else "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": None,
                      "kernel": "k_closure_rates_mfma + k_step_2d<1,closure>" if fp16 else
                                "k_closure_rates_valu + k_step_2d<1,closure>",
-                     "alg_bytes_per_launch": alg, "avg_launch_us": c["ms"] * 1e3 / max(1, c["steps"]),
+                     "alg_bytes_per_launch": bytes_per_cell("2d", 1) * cells,
+                     "avg_launch_us": c["ms"] * 1e3 / max(1, c["steps"]),
                      "note": "network flops over the whole level-1 + closure step time"},
-        "closure": {"level8_ms": ms8, "level8_steps": n8, "level8_cell_updates_per_s": cells * n8 / (ms8 * 1e-3),
-                    "smallest_plain_level_at_closure_error": equal,
-                    "level8_err_budget": {"err_h": pl["err_h"], "err_hu": pl["err_hu"]}, **results},
+        "closure": cmp_,
         "cpu_baseline": None,
     }
+    mlp.close()
     print(json.dumps(out), flush=True)
 
 

@@ -144,10 +144,15 @@ def _project_any(problem8):
 
 
 def _project_state(q8, problem8):
-    """(h, q_0, q_1) of each direction block of a level-8 state."""
+    """(h, q_0, q_1) of each direction block of a level-8 state (numpy array,
+    or torch tensor kept on its device)."""
+    n8 = problem8["level"] + 1
+    if isinstance(q8, torch.Tensor):
+        if problem8["kind"] == "1d":
+            return q8[:3].contiguous()
+        return torch.cat([q8[:3], q8[1 + n8:1 + n8 + 2]]).contiguous()
     if problem8["kind"] == "1d":
         return np.ascontiguousarray(q8[:3])
-    n8 = problem8["level"] + 1
     return np.ascontiguousarray(np.concatenate([q8[:3], q8[1 + n8:1 + n8 + 2]]))
 
 

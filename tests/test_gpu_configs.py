@@ -1,0 +1,132 @@
+"""The workload configurations run in full against the oracle.
+
+* the 1024^2 level-2 periodic grid, all 200 steps, element by element;
+* the 4M-triangle level-3 dam break with walls, all 100 steps, element by
+  element (about two minutes of oracle time on the host cores);
+* the ensemble with grid sides up to 512 at every level 1..4, each grid
+  against the oracle run alone;
+* the learned closure on a 2D grid: trained on 1D level-8 runs of the same
+  spacing, level 1 + closure must cut the relative L1 error of (h, hu)
+  against level 8 (gain < 1, and within twice the plain level-1 error).
+Metric per field: max |gpu - oracle| / max |oracle| <= 1e-10.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import sme as orc
+from paper_2601_04826_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sme():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2601_04826_amd import sme as m
+
+    return m
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def rel_linf(gpu, ref):
+    worst = 0.0
+    for f in range(ref.shape[0]):
+        scale = np.max(np.abs(ref[f]))
+        if scale == 0.0:
+            assert np.all(gpu[f] == 0.0), f"field {f} must be exactly zero"
+            continue
+        worst = max(worst, np.max(np.abs(gpu[f] - ref[f])) / scale)
+    return worst
+
+
+def full_run(sme, p):
+    say(f"full run {p['kind']} level {p['level']} cells {p['ncells']} steps {p['steps']}")
+    s = sme.Solver(p)
+    s.set_state(p["q"])
+    t_gpu, n = s.run(p["steps"])
+    q_gpu = s.get_state()
+    s.close()
+    assert n == p["steps"]
+    q_orc, t_orc = orc.from_problem(p).run(p["q"], p["steps"])
+    say(f"  oracle done, t = {t_orc:.6g}")
+    return q_gpu, q_orc, t_gpu, t_orc
+
+
+def test_struct_2d_1024_full_200_steps(sme):
+    p = W.struct_2d()
+    q_gpu, q_orc, t_gpu, t_orc = full_run(sme, p)
+    assert rel_linf(q_gpu, q_orc) <= 1e-10
+    assert abs(t_gpu - t_orc) <= 1e-11 * t_orc
+
+
+def test_tri_4m_full_100_steps(sme):
+    p = W.tri_2d()
+    q_gpu, q_orc, t_gpu, t_orc = full_run(sme, p)
+    assert rel_linf(q_gpu, q_orc) <= 1e-10
+    assert abs(t_gpu - t_orc) <= 1e-11 * t_orc
+
+
+def test_batch_large_sides_every_level(sme):
+    probs = []
+    for k, (side, level) in enumerate([(512, 1), (512, 2), (512, 3), (512, 4), (480, 4), (301, 2), (64, 1),
+                                       (100, 3)]):
+        p = W.batch(n_inst=1, seed=300 + k, steps=40, side=(side, side), levels=(level, level))[0]
+        probs.append(p)
+    say("batch sides " + str([p["nx"] for p in probs]) + " levels " + str([p["level"] for p in probs]))
+    bt = sme.Batch(probs)
+    for i, p in enumerate(probs):
+        bt.set_state(i, p["q"])
+    bt.run(40)
+    for i, p in enumerate(probs):
+        q_orc, t_orc = orc.from_problem(p).run(p["q"], 40)
+        assert rel_linf(bt.get_state(i), q_orc) <= 1e-10, i
+        t, n = bt.time(i)
+        assert n == 40 and abs(t - t_orc) <= 1e-12 * t_orc
+    bt.close()
+
+
+def test_closure_gain_on_2d_grid(sme):
+    """Reduced form of the closure evaluation: 1D level-8 training runs at the
+    spacing of a 512^2 grid on [0, 10]^2, then the smooth 2D field of the
+    evaluation family on that grid, level 1 + closure (through the fallback
+    policy) against plain level 1, both against level 8 at the time of 150
+    level-8 steps.  (On a 256^2 grid the a-priori closure trained at that
+    spacing makes the error worse: it is not used below 512 cells per 10 m.)"""
+    from paper_2601_04826_amd import closure
+
+    n = 512
+    feat, targ = closure.generate(range(1000, 1024), n=n, steps=600, every=3, cells_per_snapshot=64)
+    mlp, sc, hist = closure.fit(feat, targ, epochs=12, batch=4096, lr=3e-3, lr_end=1e-4, seed=0)
+    assert hist[-1] < hist[0]
+    p8 = W.smooth_2d(n=n, level=8, seed=2000)
+    s8 = sme.Solver(p8)
+    s8.set_state(p8["q"])
+    T, _ = s8.run(150)
+    ref = s8.get_state()
+    s8.close()
+    errs = {}
+    for name, net in (("plain", None), ("closure", mlp)):
+        cs = closure.ClosureSolver(p8, net if net is not None else sme.MLP(np.zeros(sme.NPARAM, np.float32)),
+                                   chunk=50)
+        cs.set_state(p8["q"])
+        out = cs.run_to(T)
+        assert cs.fell_back_at is None
+        say(f"{name}: out-of-range cell-steps {cs.s1.out_of_range()} of {cs.steps * p8['ncells']}")
+        cs.close()
+        e = closure.relative_l1(out, ref, fields=(0, 1))
+        errs[name] = e[0] + e[1]
+        say(f"{name}: E_h {e[0]:.3e} E_hu {e[1]:.3e}")
+    gain = errs["closure"] / errs["plain"]
+    say(f"2D closure gain {gain:.3f}")
+    assert gain < 0.6
+    assert errs["closure"] <= 2.0 * errs["plain"]
+    mlp.close()
