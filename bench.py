@@ -37,8 +37,8 @@ def bytes_per_cell(kind, level):
     nf = level + 2 if kind == "1d" else 2 * level + 3
     b = nf * 8 * 2 + 8
     if kind == "tri":
-        # + 3 int32 neighbour ids, 3 x (n_x, n_y, |e|/|V|) FP64 per cell
-        b += 3 * 4 + 9 * 8
+        # + 3 int32 neighbour ids, 3 scaled normals n |e| (2 FP64 each), 1/|V|
+        b += 3 * 4 + 3 * 2 * 8 + 8
     return b
 
 

@@ -48,7 +48,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_step(BatchArgs B)
         a.bc[3] = I.bc[3];
         a.rows = I.rows;
         a.nbr = nullptr;
-        a.fnx = a.fny = a.fw = nullptr;
+        a.fsx = a.fsy = a.ivol = nullptr;
         a.g = B.g;
         a.c_slip = B.c_slip;
         a.implicit = B.implicit;

@@ -36,12 +36,7 @@ __global__ __launch_bounds__(kBlock) void k_eig(StepArgs a)
             r = cfl_ratio_2d<N>(a.g, h, ih, qx, qy, a.idx, a.idy, &lmax);
         } else {
             double fnx[3], fny[3], fw[3];
-#pragma unroll
-            for (int s = 0; s < 3; ++s) {
-                fnx[s] = a.fnx[s * a.stride + i];
-                fny[s] = a.fny[s * a.stride + i];
-                fw[s] = a.fw[s * a.stride + i];
-            }
+            tri_geom(a, i, fnx, fny, fw);
             r = cfl_ratio_tri<N>(a.g, h, ih, qx, qy, fnx, fny, fw, &lmax);
         }
         // a loaded state must be physical too (step index = current step count)

@@ -25,11 +25,11 @@ __device__ __forceinline__ void frame_side(Side<N, true> &S, double h, double b,
     side_flux<N, true>(S, g);
 }
 
-// Raw state of one face's neighbour and the face geometry (normal, |e|/|V|).
+// Raw state of one face's neighbour and the face's scaled normal n |e|.
 template <int N>
 struct Gather {
     double h, b, qx[N + 1], qy[N + 1];
-    double nx, ny, w;
+    double sx, sy;
 };
 
 // Loads for the face at geometry index gi whose neighbour is j (a wall if j < 0:
@@ -38,9 +38,8 @@ template <int N>
 __device__ __forceinline__ void gather(const StepArgs &a, int j, int64_t gi, Gather<N> &G)
 {
     constexpr int n = N + 1;
-    G.nx = a.fnx[gi];
-    G.ny = a.fny[gi];
-    G.w = a.fw[gi];
+    G.sx = a.fsx[gi];
+    G.sy = a.fsy[gi];
     if (j >= 0) {
         G.h = a.q[j];
         G.b = a.b[j];
@@ -75,6 +74,7 @@ __global__ __launch_bounds__(kBlock) void k_step_tri(StepArgs a)
         double h0, b0, qx0[n], qy0[n];
         h0 = a.q[i];
         b0 = a.b[i];
+        const double iv = a.ivol[i];
 #pragma unroll
         for (int k = 0; k < n; ++k) {
             qx0[k] = a.q[(1 + k) * a.stride + i];
@@ -96,7 +96,8 @@ __global__ __launch_bounds__(kBlock) void k_step_tri(StepArgs a)
             const Gather<N> cur = nxt;
             if (s < 2) gather<N>(a, s == 0 ? jn[1] : jn[2], i + (s + 1) * a.stride, nxt);
             const int j = s == 0 ? jn[0] : (s == 1 ? jn[1] : jn[2]);
-            const double nx = cur.nx, ny = cur.ny, w = cur.w;
+            double nx, ny, w;
+            face_geom(cur.sx, cur.sy, iv, nx, ny, w);
             double h1, b1, qx1[n], qy1[n];
             if (j >= 0) {
                 h1 = cur.h;
@@ -164,12 +165,7 @@ __global__ __launch_bounds__(kBlock) void k_step_tri(StepArgs a)
         }
         flag_bad(a, bad);
         double fw[3], fnx[3], fny[3];  // reloaded (cached) rather than held across the face loop
-#pragma unroll
-        for (int s = 0; s < 3; ++s) {
-            fnx[s] = a.fnx[s * a.stride + i];
-            fny[s] = a.fny[s * a.stride + i];
-            fw[s] = a.fw[s * a.stride + i];
-        }
+        tri_geom(a, i, fnx, fny, fw);
         double lm;
         r = cfl_ratio_tri<N>(a.g, h, ih, qx, qy, fnx, fny, fw, &lm);
         if (!(r >= 0.0)) r = 0.0;

@@ -62,7 +62,8 @@ struct StepArgs {
     int rows;            // rows per wave strip (structured 2D)
     // triangles (internal order)
     const int32_t *nbr;  // [3][stride]
-    const double *fnx, *fny, *fw;  // [3][stride], fw = |e| / |V|
+    const double *fsx, *fsy;  // [3][stride] scaled outward normals n |e| of the faces
+    const double *ivol;       // [stride] 1 / |V|
     // model
     double g, c_slip, nu, cfl;
     int implicit;        // friction step: 0 forward Euler, 1 backward Euler

@@ -65,7 +65,7 @@ struct sme_ctx {
     double *q[2] = {nullptr, nullptr};
     double *b = nullptr;
     int32_t *nbr = nullptr;
-    double *fnx = nullptr, *fny = nullptr, *fw = nullptr;
+    double *fsx = nullptr, *fsy = nullptr, *ivol = nullptr;
     double *cx = nullptr, *cy = nullptr;  // triangle centroids (3D lifting)
     int64_t *to_internal = nullptr;  // caller cell -> internal cell (triangles)
     int64_t *to_caller = nullptr;    // internal cell -> caller cell
@@ -168,20 +168,22 @@ int check_mesh(const sme_mesh *m, int level, int *nf, int64_t *nc)
     }
 }
 
-// Triangle geometry in caller order: neighbour (or -1 = wall), outward unit
-// normal, |e| / |V| for face s = edge (v_s, v_{s+1}).
+// Triangle geometry in caller order: neighbour (or -1 = wall) and scaled
+// outward normal n |e| = (ey, -ex) for face s = edge (v_s, v_{s+1}), 1 / |V|
+// per triangle.  A shared edge is traversed in opposite directions by its two
+// triangles, so their scaled normals are exact negatives of each other.
 struct TriGeom {
     std::vector<int32_t> nbr;
-    std::vector<double> nx, ny, w;
+    std::vector<double> sx, sy, ivol;
 };
 
 int build_tri(sme_ctx *c, const sme_mesh *m, TriGeom &g)
 {
     const int64_t nt = m->n_tri, nv = m->n_vert;
     g.nbr.assign(3 * nt, -1);
-    g.nx.resize(3 * nt);
-    g.ny.resize(3 * nt);
-    g.w.resize(3 * nt);
+    g.sx.resize(3 * nt);
+    g.sy.resize(3 * nt);
+    g.ivol.resize(nt);
     const double *X = m->vert_xy;
     const int32_t *T = m->tri;
     for (int64_t t = 0; t < nt; ++t) {
@@ -194,14 +196,14 @@ int build_tri(sme_ctx *c, const sme_mesh *m, TriGeom &g)
         double area = 0.5 * ((bx - ax) * (cy - ay) - (cx - ax) * (by - ay));
         if (!(area > 0.0))
             return fail(c, SME_EMESH, "triangle %lld is degenerate or not counter-clockwise", (long long)t);
+        g.ivol[t] = 1.0 / area;
         for (int s = 0; s < 3; ++s) {
             int32_t p0 = v[s], p1 = v[(s + 1) % 3];
             double ex = X[2 * p1] - X[2 * p0];
             double ey = X[2 * p1 + 1] - X[2 * p0 + 1];
-            double len = std::sqrt(ex * ex + ey * ey);
-            g.nx[3 * t + s] = ey / len;
-            g.ny[3 * t + s] = -ex / len;
-            g.w[3 * t + s] = len / area;
+            if (!(ex != 0.0 || ey != 0.0)) return fail(c, SME_EMESH, "triangle %lld has an edge of zero length", (long long)t);
+            g.sx[3 * t + s] = ey;
+            g.sy[3 * t + s] = -ex;
         }
     }
     // match half-edges: key (min, max) vertex pair
@@ -324,9 +326,9 @@ StepArgs make_args(const sme_ctx *c)
     for (int s = 0; s < 4; ++s) a.bc[s] = c->bc[s];
     a.rows = c->rows;
     a.nbr = c->nbr;
-    a.fnx = c->fnx;
-    a.fny = c->fny;
-    a.fw = c->fw;
+    a.fsx = c->fsx;
+    a.fsy = c->fsy;
+    a.ivol = c->ivol;
     a.g = c->p.g;
     a.c_slip = c->p.c_slip;
     a.implicit = c->p.implicit_friction;
@@ -573,7 +575,7 @@ int sme_init(sme_ctx **out, int level, const sme_mesh *mesh, const sme_params *p
             std::vector<int64_t> inv(nc);
             for (int64_t k = 0; k < nc; ++k) inv[order[k]] = k;
             std::vector<int32_t> nb(3 * c->stride, -1);
-            std::vector<double> fx(3 * c->stride, 0.0), fy(3 * c->stride, 0.0), fw(3 * c->stride, 0.0);
+            std::vector<double> fx(3 * c->stride, 0.0), fy(3 * c->stride, 0.0), iv(c->stride, 0.0);
             std::vector<double> ccx(c->stride, 0.0), ccy(c->stride, 0.0);
             for (int64_t k = 0; k < nc; ++k) {
                 int64_t t = order[k];
@@ -581,18 +583,18 @@ int sme_init(sme_ctx **out, int level, const sme_mesh *mesh, const sme_params *p
                     ccx[k] += mesh->vert_xy[2 * mesh->tri[3 * t + s]] / 3.0;
                     ccy[k] += mesh->vert_xy[2 * mesh->tri[3 * t + s] + 1] / 3.0;
                 }
+                iv[k] = g.ivol[t];
                 for (int s = 0; s < 3; ++s) {
                     int32_t v = g.nbr[3 * t + s];
                     nb[s * c->stride + k] = v >= 0 ? (int32_t)inv[v] : -1;
-                    fx[s * c->stride + k] = g.nx[3 * t + s];
-                    fy[s * c->stride + k] = g.ny[3 * t + s];
-                    fw[s * c->stride + k] = g.w[3 * t + s];
+                    fx[s * c->stride + k] = g.sx[3 * t + s];
+                    fy[s * c->stride + k] = g.sy[3 * t + s];
                 }
             }
             rc = rc ? rc : dalloc(c, &c->nbr, 3 * c->stride);
-            rc = rc ? rc : dalloc(c, &c->fnx, 3 * c->stride);
-            rc = rc ? rc : dalloc(c, &c->fny, 3 * c->stride);
-            rc = rc ? rc : dalloc(c, &c->fw, 3 * c->stride);
+            rc = rc ? rc : dalloc(c, &c->fsx, 3 * c->stride);
+            rc = rc ? rc : dalloc(c, &c->fsy, 3 * c->stride);
+            rc = rc ? rc : dalloc(c, &c->ivol, c->stride);
             rc = rc ? rc : dalloc(c, &c->to_internal, nc);
             rc = rc ? rc : dalloc(c, &c->to_caller, nc);
             rc = rc ? rc : dalloc(c, &c->cx, c->stride);
@@ -600,9 +602,9 @@ int sme_init(sme_ctx **out, int level, const sme_mesh *mesh, const sme_params *p
             if (!rc) {
                 hipError_t e = hipSuccess;
                 if (e == hipSuccess) e = hipMemcpy(c->nbr, nb.data(), nb.size() * sizeof(int32_t), hipMemcpyHostToDevice);
-                if (e == hipSuccess) e = hipMemcpy(c->fnx, fx.data(), fx.size() * sizeof(double), hipMemcpyHostToDevice);
-                if (e == hipSuccess) e = hipMemcpy(c->fny, fy.data(), fy.size() * sizeof(double), hipMemcpyHostToDevice);
-                if (e == hipSuccess) e = hipMemcpy(c->fw, fw.data(), fw.size() * sizeof(double), hipMemcpyHostToDevice);
+                if (e == hipSuccess) e = hipMemcpy(c->fsx, fx.data(), fx.size() * sizeof(double), hipMemcpyHostToDevice);
+                if (e == hipSuccess) e = hipMemcpy(c->fsy, fy.data(), fy.size() * sizeof(double), hipMemcpyHostToDevice);
+                if (e == hipSuccess) e = hipMemcpy(c->ivol, iv.data(), iv.size() * sizeof(double), hipMemcpyHostToDevice);
                 if (e == hipSuccess) e = hipMemcpy(c->to_internal, inv.data(), nc * sizeof(int64_t), hipMemcpyHostToDevice);
                 if (e == hipSuccess) e = hipMemcpy(c->to_caller, order.data(), nc * sizeof(int64_t), hipMemcpyHostToDevice);
                 if (e == hipSuccess) e = hipMemcpy(c->cx, ccx.data(), ccx.size() * sizeof(double), hipMemcpyHostToDevice);
@@ -1007,9 +1009,9 @@ void sme_destroy(sme_ctx *c)
     drop_graphs(c);
     (void)hipFree(c->b);
     (void)hipFree(c->nbr);
-    (void)hipFree(c->fnx);
-    (void)hipFree(c->fny);
-    (void)hipFree(c->fw);
+    (void)hipFree(c->fsx);
+    (void)hipFree(c->fsy);
+    (void)hipFree(c->ivol);
     (void)hipFree(c->cx);
     (void)hipFree(c->cy);
     (void)hipFree(c->to_internal);

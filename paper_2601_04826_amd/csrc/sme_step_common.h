@@ -169,6 +169,27 @@ __device__ __forceinline__ double cfl_ratio_2d(double g, double h, double ih, co
     return lx * idx + ly * idy;
 }
 
+// Unit normal and |e| / |V| of a triangle face from its scaled normal
+// (sx, sy) = n |e| and the cell's 1 / |V|.  The two cells of a face hold
+// exactly opposite scaled normals, so they derive exactly opposite unit
+// normals.
+__device__ __forceinline__ void face_geom(double sx, double sy, double ivol, double &nx, double &ny, double &w)
+{
+    const double el = sqrt_pos(fma(sx, sx, sy * sy));
+    const double iel = rcp(el);
+    nx = sx * iel;
+    ny = sy * iel;
+    w = el * ivol;
+}
+
+// geometry of the three faces of triangle i (internal order)
+__device__ __forceinline__ void tri_geom(const StepArgs &a, int64_t i, double *nx, double *ny, double *w)
+{
+    const double iv = a.ivol[i];
+#pragma unroll
+    for (int s = 0; s < 3; ++s) face_geom(a.fsx[s * a.stride + i], a.fsy[s * a.stride + i], iv, nx[s], ny[s], w[s]);
+}
+
 template <int N>
 __device__ __forceinline__ double cfl_ratio_tri(double g, double h, double ih, const double *qx, const double *qy,
                                                 const double *fnx, const double *fny, const double *fw,

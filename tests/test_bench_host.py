@@ -13,7 +13,7 @@ def test_bytes_per_cell():
     assert bench.bytes_per_cell("2d", 8) == (19 * 2 + 1) * 8 == 312
     assert bench.bytes_per_cell("1d", 1) == (3 * 2 + 1) * 8 == 56
     # triangles add 3 int32 neighbours and 3 x (n_x, n_y, |e|/|V|) FP64
-    assert bench.bytes_per_cell("tri", 3) == (9 * 2 + 1) * 8 + 12 + 72 == 236
+    assert bench.bytes_per_cell("tri", 3) == (9 * 2 + 1) * 8 + 12 + 48 + 8 == 220
 
 
 def test_counter_figures_follow_the_source_hash(tmp_path, monkeypatch):
