@@ -96,6 +96,29 @@ def load_flops(workload):
     return d.get("fp64_flops_per_launch")
 
 
+def copy_rate(torch, stream, nbytes, reps=20):
+    """GB/s of a plain device copy moving nbytes in total (half read, half
+    written), timed with HIP events on the same stream: the bandwidth that a
+    kernel streaming the same bytes can practically reach at this size (the
+    256 MB last-level cache holds part of a small working set)."""
+    n = max(1, nbytes // 16)
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    with torch.cuda.stream(stream):
+        for _ in range(3):
+            dst.copy_(src)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            dst.copy_(src)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    return 2 * n * 8 / (ms * 1e-3) / 1e9
+
+
 def cpu_baseline(problem, seconds=15.0):
     """The oracle, as is, on a bounded number of steps of the same grid."""
     from oracle import sme as orc
@@ -201,6 +224,7 @@ def main():
     solver.close()
     print(f"[bench] {args.steps} steps in {ms:.3f} ms (events), {wall * 1e3:.3f} ms wall; "
           f"simulated t = {t_sim:.6g} s over {nsteps} steps", file=sys.stderr, flush=True)
+    copy_gbs = copy_rate(torch, stream, bytes_per_cell(problem["kind"], problem["level"]) * problem["ncells"])
 
     ncells = problem["ncells"]
     value = ncells * args.steps / (ms * 1e-3)
@@ -228,7 +252,8 @@ def main():
                      "kernel": wl["kernel"], "alg_bytes_per_launch": alg_bytes,
                      "avg_launch_us": per_launch_s * 1e6,
                      "launch_timing": wl.get("timing", "HIP events on the step stream around the K timed steps, / K"),
-                     "single_launch_us": per_launch_ms * 1e3},
+                     "single_launch_us": per_launch_ms * 1e3,
+                     "copy_gbs_same_bytes": copy_gbs, "frac_of_copy": achieved / copy_gbs},
         "cpu_baseline": None,
     }
     flops = load_flops(args.workload)

@@ -6,6 +6,7 @@ paper_2601_04826_amd/libsme.so next to this file.
 """
 import concurrent.futures as cf
 import os
+import re
 import subprocess
 import sys
 
@@ -33,21 +34,65 @@ FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
 # read them without v_accvgpr_read copies (the unified register file has room)
 EXTRA = {"k_closure.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
+# Register-spill guard.  With machine loop-invariant code motion enabled the
+# backend hoists the FP64 tensor literals of the step kernels out of their row
+# loops and spills 290-1160 SGPRs per kernel at levels 5-8 into VGPR lanes; a
+# build in that state gave level-7/8 results that differed from run to run.
+# Every kernel's resource-usage remarks are therefore read at build time and
+# the build fails if any kernel spills more SGPRs than the level-8 structured
+# step does with the flag (255), spills any VGPR, or uses scratch memory.
+MAX_SGPR_SPILL = 255
+REMARKS = "-Rpass-analysis=kernel-resource-usage"
+
+
+def resource_usage(text):
+    """[(kernel, sgpr_spill, vgpr_spill, scratch_bytes_per_lane)] from the
+    compiler's kernel-resource-usage remarks."""
+    out, cur = [], None
+    for line in text.splitlines():
+        m = re.search(r"remark: Function Name: (\S+)", line)
+        if m:
+            cur = [m.group(1), 0, 0, 0]
+            out.append(cur)
+            continue
+        if cur is None:
+            continue
+        for key, idx in (("SGPRs Spill", 1), ("VGPRs Spill", 2), ("ScratchSize [bytes/lane]", 3)):
+            m = re.search(r"remark:\s+" + re.escape(key) + r": (\d+)", line)
+            if m:
+                cur[idx] = int(m.group(1))
+    return [tuple(x) for x in out]
+
+
+def check_spills(src, usage):
+    bad = [u for u in usage if u[1] > MAX_SGPR_SPILL or u[2] > 0 or u[3] > 0]
+    if bad:
+        lines = "\n".join(f"  {k}: SGPR spill {s}, VGPR spill {v}, scratch {sc} B/lane" for k, s, v, sc in bad)
+        raise RuntimeError(f"{src}: register spill guard failed (SGPR spill limit {MAX_SGPR_SPILL}, "
+                           f"no VGPR spill, no scratch):\n{lines}")
+
 
 def _compile(src):
     out = os.path.join(OBJ, os.path.splitext(src)[0] + ".o")
     cmd = [HIPCC] + FLAGS + EXTRA.get(src, []) + ["-c", os.path.join(CSRC, src), "-o", out]
     if src.endswith(".cpp"):
         cmd[1:1] = ["-x", "hip"]
+    else:
+        cmd.insert(1, REMARKS)
     r = subprocess.run(cmd, capture_output=True, text=True)
-    msgs = "\n".join(l for l in (r.stdout + r.stderr).splitlines()
-                     if "packed-fp32-ops" not in l)
+    text = r.stdout + r.stderr
+    msgs = "\n".join(l for l in text.splitlines()
+                     if "packed-fp32-ops" not in l and "kernel-resource-usage" not in l)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{msgs}")
+    if src.endswith(".hip"):
+        check_spills(src, resource_usage(text))
     return out, msgs
 
 
 def build(jobs=None, verbose=False):
+    if "-disable-machine-licm" not in FLAGS:
+        raise RuntimeError("the step kernels are built with -mllvm -disable-machine-licm (see the spill guard)")
     os.makedirs(OBJ, exist_ok=True)
     jobs = jobs or min(len(SOURCES), os.cpu_count() or 4)
     with cf.ThreadPoolExecutor(jobs) as ex:
