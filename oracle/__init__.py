@@ -12,4 +12,6 @@ mesh      generic cell/face lists for 1D, 2D structured and triangle meshes
 sme       ctypes driver around ``sme_oracle.c`` (flux, NC matrix, step, CFL)
 stoker    exact Riemann solution of the wet dam break (level-0 pin)
 mlp       FP64 MLP forward/backward/Adam for the learned closure
+lift      3D lifting of a state (sigma levels: z, u, v, w, p)
+vam       non-hydrostatic VAM predictor-corrector step in 1D (numpy, sparse solve)
 """

@@ -216,3 +216,27 @@ def batch(n_inst=512, seed=4, steps=500, side=(64, 512), levels=(1, 4), params=N
         out.append(_problem("2d", level, n * n, q, np.zeros(n * n), steps, params,
                             nx=n, ny=n, x0=0.0, x1=1.0, y0=0.0, y1=1.0, bc=("wall",) * 4))
     return out
+
+def vam_1d(n=2000, L=20.0, steps=200, seed=7, params=None, moments=True):
+    """1D channel for the non-hydrostatic VAM step: a smoothed 0.3 m dam
+    (undular bore) upstream of a 0.2 m Gaussian hump, still water level 1 m
+    downstream, extrapolation ends; fields (h, h u0, h u1, h w0, h w1).  With
+    `moments`, small seeded smooth profiles of u1, w0 and w1 are added so that
+    every field of the step is active."""
+    rng = np.random.default_rng(seed)
+    dx = L / n
+    x = (np.arange(n) + 0.5) * dx
+    b = 0.2 * np.exp(-((x - 0.6 * L) / (0.05 * L)) ** 2)
+    eta = 1.0 + 0.15 * (1.0 - np.tanh((x - 0.3 * L) / (0.01 * L)))
+    h = eta - b
+    q = np.zeros((5, n))
+    q[0] = h
+    q[1] = h * 0.2 * (1.0 - np.tanh((x - 0.3 * L) / (0.01 * L)))
+    if moments:
+        for f, amp in ((2, 0.05), (3, 0.02), (4, 0.02)):
+            k = rng.integers(1, 4)
+            q[f] = h * amp * rng.uniform(0.5, 1.0) * np.sin(2 * np.pi * k * x / L + rng.uniform(0, 2 * np.pi))
+    p = dict(g=9.81, cfl=0.45, quad_points=3)
+    if params:
+        p.update(params)
+    return dict(kind="vam", ncells=n, nx=n, x0=0.0, x1=L, q=q, b=b, steps=steps, params=p)
