@@ -279,6 +279,53 @@ const char *sme_batch_last_error(const sme_batch *bt);
 void sme_batch_destroy(sme_batch *bt);
 
 /* ------------------------------------------------------------------------
+ * Non-hydrostatic VAM channel (Sec. 3.3, the predictor-corrector splitting of
+ * Sec. 2.1.2): the 1D vertically averaged momentum equations with linear u,
+ * quadratic w and quadratic non-hydrostatic pressure, fields (h, h u0, h u1,
+ * h w0, h w1) on nx uniform cells of [x0, x1] with extrapolation ends.  A step
+ * is the explicit hydrostatic predictor (path-conservative Rusanov with the
+ * model's flux and non-conservative product, the bed entering as g h b_x)
+ * followed by the corrector: the pressure (p0, p1) for which the two
+ * incompressibility constraints hold at the corrected state, found by one
+ * linear solve (the constraints are affine in the pressure), then the
+ * pressure source applied.  Spatial derivatives of the corrector are central
+ * differences.  No friction (the paper's VAM case has none).
+ *
+ * Ownership as for sme_init: the caller owns the two state buffers, SoA
+ * [5][field_stride] FP64 device memory, 256-byte aligned, field_stride from
+ * sme_vam_layout; the library allocates sme_vam_workspace_size bytes (the
+ * bathymetry, the pressure, the corrector's two block systems, the slots).
+ * All work is queued on `stream`.  Errors: SME_EINVAL (size, pointer or
+ * parameter), SME_ENOMEM, SME_EHIP, SME_ENONPHYS (h <= 0 or a non-finite value,
+ * reported by the calls that synchronise); sme_vam_last_error gives the text.
+ */
+typedef struct sme_vam sme_vam;
+
+int sme_vam_layout(int64_t nx, int64_t *field_stride);
+int sme_vam_workspace_size(int64_t nx, size_t *bytes);
+/* g > 0, cfl > 0, quad_points 1..8 (Gauss points of the path integral); b the
+ * bathymetry [nx] on the host or (b_on_device) the device, NULL = flat. */
+int sme_vam_init(sme_vam **out, int64_t nx, double x0, double x1, double g, double cfl, int quad_points,
+                 double *const q_dev[2], const double *b, int b_on_device, void *stream);
+/* state [5][nx] (host or device), or one of the two bound buffers in place;
+ * resets the clock and reduces the CFL ratio of the state */
+int sme_vam_set_state(sme_vam *v, const double *q, int on_device);
+int sme_vam_get_state(sme_vam *v, double *q, int on_device);
+/* (p0, p1) [2][nx] of the last corrector */
+int sme_vam_pressure(sme_vam *v, double *p, int on_device);
+/* one step: dt > 0 as given, else the CFL step (dt = cfl dx / max(|u0| +
+ * sqrt(g h + u1^2))) computed on the device; dt_used may be NULL */
+int sme_vam_step(sme_vam *v, double dt, double *dt_used);
+/* n_steps CFL steps, the last one shortened to end at t_end if t_end > 0
+ * (steps past t_end leave the state unchanged) */
+int sme_vam_run(sme_vam *v, int64_t n_steps, double t_end, double *t_out, int64_t *steps_done);
+int sme_vam_time(sme_vam *v, double *t, int64_t *steps);
+int sme_vam_current(const sme_vam *v);   /* which bound buffer holds the state */
+int64_t sme_vam_field_stride(const sme_vam *v);
+const char *sme_vam_last_error(const sme_vam *v);
+void sme_vam_destroy(sme_vam *v);
+
+/* ------------------------------------------------------------------------
  * Learned closure: a small network (9 -> 64 -> 64 -> 2, tanh, FP32 training
  * and inference kernels) that corrects the level-1 step towards level 8.  The
  * paper has no learned closure; its level hierarchy (Eq. (1), Sec. 3.4) is

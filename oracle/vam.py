@@ -154,23 +154,30 @@ class Vam1D:
         zero = np.zeros((2, n))
         r = self.residual(self.correct_state(Qs, zero, dt)).ravel()
         rows, cols, vals = [], [], []
-        ncol = 5 if n >= 5 else n
+        if n >= 5:
+            assert not self.periodic or n % 5 == 0, "periodic colouring needs nx divisible by 5"
+            ncol = 5
+        else:
+            ncol = n
         for comp in range(2):
             for c in range(ncol):
                 P = np.zeros((2, n))
                 P[comp, c::ncol] = 1.0
                 dR = self.residual(self.correct_state(Qs, P, dt)).ravel() - r
-                for row in np.nonzero(dR)[0]:
-                    cell = row % n
-                    # the probed cell of this colour within two cells of `cell`
-                    cand = [m for m in range(cell - 2, cell + 3)
-                            if (m % n if self.periodic else m) % ncol == c and 0 <= (m % n if self.periodic else m) < n]
-                    assert len(cand) == 1, (row, c, cand)
-                    m = cand[0] % n
-                    rows.append(row)
-                    cols.append(comp * n + m)
-                    vals.append(dR[row])
-        J = scipy.sparse.csr_matrix((vals, (rows, cols)), shape=(2 * n, 2 * n))
+                row = np.nonzero(dR)[0]
+                cell = row % n
+                # the one probed cell of colour c within two cells of `cell`
+                if ncol == 5:
+                    m = cell + ((c - cell + 2) % 5) - 2
+                    m = m % n if self.periodic else m
+                    assert np.all((m >= 0) & (m < n) & (np.abs(m - cell) % n <= 2) | (np.abs(m - cell) >= n - 2))
+                else:
+                    m = np.full_like(cell, c)
+                rows.append(row)
+                cols.append(comp * n + m)
+                vals.append(dR[row])
+        J = scipy.sparse.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                                    shape=(2 * n, 2 * n))
         return J, r
 
     def correct(self, Qs, dt):

@@ -17,8 +17,8 @@ LIB = os.path.join(HERE, "libsme.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 SOURCES = ["k_step_1d.hip", "k_step_2d.hip", "k_step_tri.hip", "k_batch.hip", "k_misc.hip", "k_mlp.hip", "k_closure.hip",
-           "k_lift.hip", "k_step2.hip",
-           "sme_lib.cpp", "sme_batch.cpp", "sme_closure.cpp", "sme_static.cpp", "sme_mesh.cpp"]
+           "k_lift.hip", "k_step2.hip", "k_vam.hip",
+           "sme_lib.cpp", "sme_batch.cpp", "sme_closure.cpp", "sme_static.cpp", "sme_mesh.cpp", "sme_vam.cpp"]
 FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
          # no packed FP32 instructions anywhere in the device code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

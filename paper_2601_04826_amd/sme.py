@@ -38,6 +38,9 @@ EXPORTS = [
     "sme_mlp_loss_grad", "sme_mlp_train_step", "sme_mlp_reset_optimizer", "sme_mlp_last_error", "sme_mlp_destroy",
     "sme_closure_samples", "sme_closure_attach", "sme_closure_attach_ex", "sme_closure_out_of_range",
     "sme_closure_train", "sme_closure_run",
+    "sme_vam_layout", "sme_vam_workspace_size", "sme_vam_init", "sme_vam_set_state", "sme_vam_get_state",
+    "sme_vam_pressure", "sme_vam_step", "sme_vam_run", "sme_vam_time", "sme_vam_current", "sme_vam_field_stride",
+    "sme_vam_last_error", "sme_vam_destroy",
 ]
 
 
@@ -119,6 +122,19 @@ def _load():
         "sme_closure_out_of_range": (i, [vp, P(i64)]),
         "sme_closure_train": (i, [vp, vp, vp, i64, i, i64, ctypes.c_float, ctypes.c_float, ctypes.c_uint64, d, vp]),
         "sme_closure_run": (i, [vp, vp, d, i64, i64, d, P(d), P(i64), P(d)]),
+        "sme_vam_layout": (i, [i64, P(i64)]),
+        "sme_vam_workspace_size": (i, [i64, P(ctypes.c_size_t)]),
+        "sme_vam_init": (i, [P(vp), i64, d, d, d, d, i, P(vp), vp, i, vp]),
+        "sme_vam_set_state": (i, [vp, vp, i]),
+        "sme_vam_get_state": (i, [vp, vp, i]),
+        "sme_vam_pressure": (i, [vp, vp, i]),
+        "sme_vam_step": (i, [vp, d, P(d)]),
+        "sme_vam_run": (i, [vp, i64, d, P(d), P(i64)]),
+        "sme_vam_time": (i, [vp, P(d), P(i64)]),
+        "sme_vam_current": (i, [vp]),
+        "sme_vam_field_stride": (i64, [vp]),
+        "sme_vam_last_error": (ctypes.c_char_p, [vp]),
+        "sme_vam_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -597,3 +613,84 @@ def closure_run(s1, s8, t_end, chunk, max_steps, max_out_of_range):
     _check(_lib.sme_closure_run(s1.ctx, s8.ctx, float(t_end), int(chunk), int(max_steps), float(max_out_of_range),
                                 ctypes.byref(t), ctypes.byref(n), ctypes.byref(fb)), s1.ctx)
     return t.value, n.value, (fb.value if fb.value >= 0 else None)
+
+
+# ---------------------------------------------------------------------------
+# Non-hydrostatic VAM channel (include/sme.h, sme_vam_*)
+def _vcheck(code, ctx=None):
+    if code != SME_OK:
+        msg = (_lib.sme_vam_last_error(ctx) or b"").decode() if ctx else ""
+        raise SmeError(code, msg or _lib.sme_strerror(code).decode())
+
+
+def sme_vam_layout(nx):
+    st = ctypes.c_int64()
+    _vcheck(_lib.sme_vam_layout(int(nx), ctypes.byref(st)))
+    return st.value
+
+
+def sme_vam_workspace_size(nx):
+    n = ctypes.c_size_t()
+    _vcheck(_lib.sme_vam_workspace_size(int(nx), ctypes.byref(n)))
+    return n.value
+
+
+class Vam:
+    """A VAM channel bound to two torch state tensors [5, field_stride]
+    (fields h, h u0, h u1, h w0, h w1), problem dict from workloads.vam_1d."""
+
+    def __init__(self, problem, stream=None, **overrides):
+        prm = dict(problem["params"])
+        prm.update(overrides)
+        self.nx = int(problem["nx"])
+        st = sme_vam_layout(self.nx)
+        self.q_dev = [torch.zeros((5, st), dtype=torch.float64, device="cuda") for _ in range(2)]
+        qp = (ctypes.c_void_p * 2)(self.q_dev[0].data_ptr(), self.q_dev[1].data_ptr())
+        b = np.ascontiguousarray(problem["b"], dtype=np.float64)
+        self.ctx = ctypes.c_void_p()
+        torch.cuda.synchronize()
+        _vcheck(_lib.sme_vam_init(ctypes.byref(self.ctx), self.nx, float(problem["x0"]), float(problem["x1"]),
+                                  float(prm["g"]), float(prm["cfl"]), int(prm["quad_points"]), qp,
+                                  b.ctypes.data_as(ctypes.c_void_p), 0, stream))
+
+    def set_state(self, q):
+        if isinstance(q, torch.Tensor):
+            q = q.contiguous()
+            torch.cuda.synchronize()
+            _vcheck(_lib.sme_vam_set_state(self.ctx, ctypes.c_void_p(q.data_ptr()), 1), self.ctx)
+        else:
+            q = np.ascontiguousarray(q, dtype=np.float64)
+            _vcheck(_lib.sme_vam_set_state(self.ctx, q.ctypes.data_as(ctypes.c_void_p), 0), self.ctx)
+
+    def get_state(self):
+        out = np.empty((5, self.nx))
+        _vcheck(_lib.sme_vam_get_state(self.ctx, out.ctypes.data_as(ctypes.c_void_p), 0), self.ctx)
+        return out
+
+    def pressure(self):
+        out = np.empty((2, self.nx))
+        _vcheck(_lib.sme_vam_pressure(self.ctx, out.ctypes.data_as(ctypes.c_void_p), 0), self.ctx)
+        return out
+
+    def step(self, dt=0.0):
+        used = ctypes.c_double()
+        _vcheck(_lib.sme_vam_step(self.ctx, float(dt), ctypes.byref(used)), self.ctx)
+        return used.value
+
+    def run(self, n_steps, t_end=0.0):
+        t, k = ctypes.c_double(), ctypes.c_int64()
+        _vcheck(_lib.sme_vam_run(self.ctx, int(n_steps), float(t_end), ctypes.byref(t), ctypes.byref(k)), self.ctx)
+        return t.value, k.value
+
+    def time(self):
+        t, k = ctypes.c_double(), ctypes.c_int64()
+        _vcheck(_lib.sme_vam_time(self.ctx, ctypes.byref(t), ctypes.byref(k)), self.ctx)
+        return t.value, k.value
+
+    def current(self):
+        return _lib.sme_vam_current(self.ctx)
+
+    def close(self):
+        if self.ctx:
+            _lib.sme_vam_destroy(self.ctx)
+            self.ctx = ctypes.c_void_p()
