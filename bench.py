@@ -58,7 +58,43 @@ WORKLOADS = {
                       name="batch_512_grids_side64-512_levels1-4_walls"),
     "closure_2048": dict(gen="closure", args={}, kernel="k_closure_rates_mfma",
                          name="closure_level1_vs_level8_2048x2048_periodic"),
+    # the non-hydrostatic VAM channel: a step is the predictor, two Newton passes of the corrector
+    # (assembly, block cyclic reduction level by level, back substitution, pressure update) and the
+    # correction
+    "vam_1d": dict(gen="vam", args=dict(n=1 << 20, L=1000.0), kernel="k_vam_cr_reduce",
+                   name="vam_1d_channel_1048576_cells_bore_over_hump"),
 }
+
+
+def vam_bytes_per_cell(nx):
+    """Algorithmic bytes per cell of one VAM step: predictor (5 fields + b in,
+    5 out), two Newton passes of the corrector -- assembly (5 fields + b
+    (+ p) in, 52 FP64 block entries per pair of cells out), block cyclic
+    reduction (at stride s the nb / s equations still active are read once,
+    the nb / 2s updated ones written), back substitution (A, B, C, d and the
+    two known neighbour blocks in, the block out), pressure update (x in, p
+    out, + p in) -- and the correction (5 fields, p, b in; 4 fields out)."""
+    nb = (nx + 1) // 2
+    top = 1
+    while 2 * top - 1 < nb:
+        top *= 2
+    reduce_d = back_d = 0
+    s = 1
+    while s < top:
+        active = (nb + 1) // s if s > 1 else nb       # equations with (k + 1) % s == 0
+        updated = nb // (2 * s)
+        reduce_d += 52 * active + 52 * updated
+        s *= 2
+    s = top
+    while s >= 1:
+        back_d += 64 * ((nb + s) // (2 * s))
+        s //= 2
+    solve_bytes = 8 * (reduce_d + back_d) + 8 * (8 * nb)  # + scatter: x in, p out
+    predict = 11 * 8 * nx
+    assemble = (6 * 8 + 26 * 8) * nx + (8 * 8 + 26 * 8) * nx
+    newton_p = 2 * 8 * nx                                  # p read by the second pass's update
+    correct = (8 * 8 + 4 * 8) * nx
+    return (predict + assemble + 2 * solve_bytes + newton_p + correct) / nx
 
 
 def source_hash():
@@ -186,6 +222,8 @@ def main():
         return bench_batch(args, wl, torch, sme, workloads)
     if wl["gen"] == "closure":
         return bench_closure(args, wl, torch, sme, workloads)
+    if wl["gen"] == "vam":
+        return bench_vam(args, wl, torch, sme, workloads)
     t0 = time.perf_counter()
     problem = getattr(workloads, wl["gen"])(**wl["args"])
     print(f"[bench] workload {wl['name']}: {problem['ncells']} cells, level {problem['level']} "
@@ -485,6 +523,64 @@ def bench_batch(args, wl, torch, sme, workloads):
         el = time.perf_counter() - t0
         out["cpu_baseline"] = dict(value=done / el, unit="cell-updates/s", cores=orc.max_threads(), kind="oracle",
                                    sample=f"one step of the first {done} cells of the ensemble ({el:.1f} s)")
+    print(json.dumps(out), flush=True)
+
+
+def bench_vam(args, wl, torch, sme, workloads):
+    """The non-hydrostatic VAM channel: K predictor-corrector steps."""
+    p = workloads.vam_1d(**wl["args"])
+    nx = p["nx"]
+    print(f"[bench] workload {wl['name']}: {nx} cells", file=sys.stderr, flush=True)
+    stream = torch.cuda.Stream()
+    v = sme.Vam(p, stream=stream.cuda_stream)
+    q0 = torch.from_numpy(p["q"]).cuda()
+    torch.cuda.synchronize()
+    v.set_state(q0)
+    v.run(args.warmup)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    t_sim, n_done = v.run(args.steps)  # synchronises at the end (error check), after ev1 is queued below
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    v.close()
+    per_step_s = ms * 1e-3 / args.steps
+    alg = int(round(vam_bytes_per_cell(nx) * nx))
+    copy_gbs = copy_rate(torch, stream, min(alg, 4 << 30))
+    out = {
+        "metric": "VAM cell-updates/s (FP64, predictor + corrector)", "value": nx * args.steps / (ms * 1e-3),
+        "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms / args.steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": wl["name"], "cells": nx, "levels_of_reduction": max(0, ((nx + 1) // 2 - 1).bit_length())},
+        "roofline": {"bound": "hbm", "achieved": alg / per_step_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": alg / per_step_s / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "one VAM step (k_vam_predict, 2 x (k_vam_assemble, k_vam_cr_reduce and k_vam_cr_back "
+                               "per level, k_vam_scatter), k_vam_correct)",
+                     "alg_bytes_per_launch": alg, "avg_launch_us": per_step_s * 1e6,
+                     "launch_timing": "HIP events on the step stream around the K timed steps, / K (a launch here "
+                                      "is one step's kernel sequence)",
+                     "copy_gbs_same_bytes": copy_gbs, "frac_of_copy": alg / per_step_s / 1e9 / copy_gbs},
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        from oracle import vam as ovam
+
+        o = ovam.Vam1D(nx, p["x0"], p["x1"], b=p["b"], g=p["params"]["g"], cfl=p["params"]["cfl"],
+                       quad_points=p["params"]["quad_points"])
+        q = p["q"]
+        steps, t0 = 0, time.perf_counter()
+        while True:
+            q, _, _ = o.step(q)
+            steps += 1
+            el = time.perf_counter() - t0
+            if el >= args.cpu_seconds or steps >= args.steps:
+                break
+        out["cpu_baseline"] = dict(value=nx * steps / el, unit="cell-updates/s", cores=1, kind="oracle",
+                                   sample=f"first {steps} steps of the same {nx}-cell channel ({el:.1f} s, numpy "
+                                          "and a sparse direct solve, one thread)")
     print(json.dumps(out), flush=True)
 
 

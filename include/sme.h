@@ -294,7 +294,7 @@ void sme_batch_destroy(sme_batch *bt);
  * Ownership as for sme_init: the caller owns the two state buffers, SoA
  * [5][field_stride] FP64 device memory, 256-byte aligned, field_stride from
  * sme_vam_layout; the library allocates sme_vam_workspace_size bytes (the
- * bathymetry, the pressure, the corrector's two block systems, the slots).
+ * bathymetry, the pressure, the corrector's block system and its solution, the slots).
  * All work is queued on `stream`.  Errors: SME_EINVAL (size, pointer or
  * parameter), SME_ENOMEM, SME_EHIP, SME_ENONPHYS (h <= 0 or a non-finite value,
  * reported by the calls that synchronise); sme_vam_last_error gives the text.

@@ -451,96 +451,132 @@ __device__ __forceinline__ void muladd4(const double *X, const double *Y, double
         }
 }
 
-// One cyclic-reduction step: block k eliminates its couplings to k -/+ s with
-// the equations of those blocks.  With a = -A_k B_{k-s}^-1 and g = -C_k B_{k+s}^-1:
-//   A' = a A_{k-s},  C' = g C_{k+s},  B' = B_k + a C_{k-s} + g A_{k+s},
-//   d' = d_k + a d_{k-s} + g d_{k+s}.
-// A block whose neighbour at distance s does not exist has no coupling to it.
-__global__ __launch_bounds__(kBlock) void k_vam_pcr(int nb, int s, VamSystem src, VamSystem dst)
+// Block cyclic reduction with the equations of every level stored apart and
+// contiguously.  Level l holds n_l equations, equation j coupled to j - 1 and
+// j + 1 of the same level.  Level l + 1 holds the odd equations of level l,
+// j = 2t + 1, each updated by eliminating its couplings with the equations
+// j - 1 and j + 1 (which then couple it to j -/+ 2, the equations t -/+ 1 of
+// level l + 1):
+//   a = -A_j B_{j-1}^-1,  g = -C_j B_{j+1}^-1,
+//   A' = a A_{j-1},  C' = g C_{j+1},  B' = B_j + a C_{j-1} + g A_{j+1},
+//   d' = d_j + a d_{j-1} + g d_{j+1};
+// an equation without a right neighbour has no coupling to it.  The one
+// equation of the top level is decoupled; back substitution then visits the
+// levels downwards: the odd unknowns of level l are those of level l + 1, the
+// even ones follow from x_j = B_j^-1 (d_j - A_j x_{j-1} - C_j x_{j+1}).
+// Every access is to consecutive equations (the compaction keeps the loads
+// coalesced at every level), and work and traffic halve from level to level.
+__global__ __launch_bounds__(kBlock) void k_vam_cr_reduce(int n, VamSystem src, VamSystem dst)
 {
-    const int k = blockIdx.x * kBlock + threadIdx.x;
-    if (k >= nb) return;
-    double Bk[16], dk[4], T[16], G[16], Z[16];
-    load4(src.B, nb, k, Bk);
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    const int nd = n / 2;
+    if (t >= nd) return;
+    const int j = 2 * t + 1;
+    double Bj[16], dj[4], T[16], G[16], Z[16];
+    load4(src.B, n, j, Bj);
 #pragma unroll
-    for (int r = 0; r < 4; ++r) dk[r] = src.d[r * nb + k];
-    if (k - s >= 0) {
-        load4(src.B, nb, k - s, T);
-        inv4(T, Z);                    // B_{k-s}^-1
-        load4(src.A, nb, k, T);
-        mul4(T, Z, G);                 // A_k B_{k-s}^-1
+    for (int r = 0; r < 4; ++r) dj[r] = src.d[r * n + j];
+    {
+        load4(src.B, n, j - 1, T);
+        inv4(T, Z);                    // B_{j-1}^-1
+        load4(src.A, n, j, T);
+        mul4(T, Z, G);                 // A_j B_{j-1}^-1
 #pragma unroll
         for (int e = 0; e < 16; ++e) G[e] = -G[e];
-        load4(src.A, nb, k - s, T);
+        load4(src.A, n, j - 1, T);
         mul4(G, T, Z);
-        store4(dst.A, nb, k, Z);
-        load4(src.C, nb, k - s, T);
-        muladd4(G, T, Bk);
+        store4(dst.A, nd, t, Z);
+        load4(src.C, n, j - 1, T);
+        muladd4(G, T, Bj);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            double acc = dk[r];
+            double acc = dj[r];
 #pragma unroll
-            for (int e = 0; e < 4; ++e) acc = fma(G[r * 4 + e], src.d[e * nb + k - s], acc);
-            dk[r] = acc;
+            for (int e = 0; e < 4; ++e) acc = fma(G[r * 4 + e], src.d[e * n + j - 1], acc);
+            dj[r] = acc;
+        }
+    }
+    if (j + 1 < n) {
+        load4(src.B, n, j + 1, T);
+        inv4(T, Z);                    // B_{j+1}^-1
+        load4(src.C, n, j, T);
+        mul4(T, Z, G);                 // C_j B_{j+1}^-1
+#pragma unroll
+        for (int e = 0; e < 16; ++e) G[e] = -G[e];
+        load4(src.C, n, j + 1, T);
+        mul4(G, T, Z);
+        store4(dst.C, nd, t, Z);
+        load4(src.A, n, j + 1, T);
+        muladd4(G, T, Bj);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            double acc = dj[r];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc = fma(G[r * 4 + e], src.d[e * n + j + 1], acc);
+            dj[r] = acc;
         }
     } else {
 #pragma unroll
         for (int e = 0; e < 16; ++e) Z[e] = 0.0;
-        store4(dst.A, nb, k, Z);
+        store4(dst.C, nd, t, Z);
     }
-    if (k + s < nb) {
-        load4(src.B, nb, k + s, T);
-        inv4(T, Z);                    // B_{k+s}^-1
-        load4(src.C, nb, k, T);
-        mul4(T, Z, G);                 // C_k B_{k+s}^-1
+    store4(dst.B, nd, t, Bj);
 #pragma unroll
-        for (int e = 0; e < 16; ++e) G[e] = -G[e];
-        load4(src.C, nb, k + s, T);
-        mul4(G, T, Z);
-        store4(dst.C, nb, k, Z);
-        load4(src.A, nb, k + s, T);
-        muladd4(G, T, Bk);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            double acc = dk[r];
-#pragma unroll
-            for (int e = 0; e < 4; ++e) acc = fma(G[r * 4 + e], src.d[e * nb + k + s], acc);
-            dk[r] = acc;
-        }
-    } else {
-#pragma unroll
-        for (int e = 0; e < 16; ++e) Z[e] = 0.0;
-        store4(dst.C, nb, k, Z);
-    }
-    store4(dst.B, nb, k, Bk);
-#pragma unroll
-    for (int r = 0; r < 4; ++r) dst.d[r * nb + k] = dk[r];
+    for (int r = 0; r < 4; ++r) dst.d[r * nd + t] = dj[r];
 }
 
-// the decoupled blocks: x_k = B_k^-1 d_k -> (p0, p1) of cells 2k, 2k + 1
-// (added to the pressure if accumulate)
-__global__ __launch_bounds__(kBlock) void k_vam_solve(VamArgs a, VamSystem m, int accumulate)
+// back substitution of level l (n equations) into x ([4][n]); xup holds the
+// unknowns of level l + 1 (null at the top level, which has one equation)
+__global__ __launch_bounds__(kBlock) void k_vam_cr_back(int n, VamSystem m, const double *xup, double *x)
 {
-    const int k = blockIdx.x * kBlock + threadIdx.x;
-    if (k >= a.nb) return;
-    double Bk[16], Bi[16], x[4];
-    load4(m.B, a.nb, k, Bk);
-    inv4(Bk, Bi);
+    const int j = blockIdx.x * kBlock + threadIdx.x;
+    if (j >= n) return;
+    const int nu = n / 2;
+    if (j & 1) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) x[r * n + j] = xup[r * nu + (j >> 1)];
+        return;
+    }
+    double rhs[4], T[16], Z[16];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) rhs[r] = m.d[r * n + j];
+    if (j >= 1) {
+        load4(m.A, n, j, T);
+        const int u = (j - 1) >> 1;  // x_{j-1} is unknown u of level l + 1
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) rhs[r] = fma(-T[r * 4 + e], xup[e * nu + u], rhs[r]);
+    }
+    if (j + 1 < n) {
+        load4(m.C, n, j, T);
+        const int u = j >> 1;        // x_{j+1}
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) rhs[r] = fma(-T[r * 4 + e], xup[e * nu + u], rhs[r]);
+    }
+    load4(m.B, n, j, T);
+    inv4(T, Z);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        double s = 0.0;
+        double v = 0.0;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) s = fma(Bi[r * 4 + e], m.d[e * a.nb + k], s);
-        x[r] = s;
+        for (int e = 0; e < 4; ++e) v = fma(Z[r * 4 + e], rhs[e], v);
+        x[r * n + j] = v;
     }
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-        const int cell = 2 * k + c;
-        if (cell < a.nx) {
-            a.p[cell] = accumulate ? a.p[cell] + x[2 * c] : x[2 * c];
-            a.p[a.stride + cell] = accumulate ? a.p[a.stride + cell] + x[2 * c + 1] : x[2 * c + 1];
-        }
-    }
+}
+
+// the solved blocks -> (p0, p1) of cells 2k, 2k + 1 (added to the pressure if
+// accumulate)
+__global__ __launch_bounds__(kBlock) void k_vam_scatter(VamArgs a, const double *x, int accumulate)
+{
+    const int cell = blockIdx.x * kBlock + threadIdx.x;
+    if (cell >= a.nx) return;
+    const int k = cell >> 1, c = cell & 1;
+    const double x0 = x[(2 * c) * a.nb + k], x1 = x[(2 * c + 1) * a.nb + k];
+    a.p[cell] = accumulate ? a.p[cell] + x0 : x0;
+    a.p[a.stride + cell] = accumulate ? a.p[a.stride + cell] + x1 : x1;
 }
 
 __global__ __launch_bounds__(kBlock) void k_vam_correct(VamArgs a)
@@ -598,15 +634,22 @@ hipError_t launch_vam_assemble(const VamArgs &a, const VamSystem &m, const doubl
     return hipGetLastError();
 }
 
-hipError_t launch_vam_pcr(const VamArgs &a, const VamSystem &src, const VamSystem &dst, int stride, hipStream_t s)
+hipError_t launch_vam_reduce(int n, const VamSystem &src, const VamSystem &dst, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_vam_pcr, dim3(blocks_for(a.nb)), dim3(kBlock), 0, s, a.nb, stride, src, dst);
+    if (n / 2 == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_vam_cr_reduce, dim3(blocks_for(n / 2)), dim3(kBlock), 0, s, n, src, dst);
     return hipGetLastError();
 }
 
-hipError_t launch_vam_solve(const VamArgs &a, const VamSystem &m, int accumulate, hipStream_t s)
+hipError_t launch_vam_back(int n, const VamSystem &m, const double *xup, double *x, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_vam_solve, dim3(blocks_for(a.nb)), dim3(kBlock), 0, s, a, m, accumulate);
+    hipLaunchKernelGGL(k_vam_cr_back, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, m, xup, x);
+    return hipGetLastError();
+}
+
+hipError_t launch_vam_scatter(const VamArgs &a, const double *x, int accumulate, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_vam_scatter, dim3(blocks_for(a.nx)), dim3(kBlock), 0, s, a, x, accumulate);
     return hipGetLastError();
 }
 

@@ -2,10 +2,10 @@
 // include/sme.h, kernels in k_vam.hip).
 //
 // Binds the caller's two state buffers, owns the bathymetry, the pressure,
-// the two block-tridiagonal systems of the corrector (ping-pong for the
-// cyclic reduction) and the time slots, and queues the kernels of a step on
-// the caller's stream: predictor, assembly, ceil(log2(blocks)) reduction
-// steps, block solve, correction.  The step size is computed on the device
+// the block-tridiagonal system of the corrector (reduced in place) and the
+// time slots, and queues the kernels of a step on the caller's stream:
+// predictor, then twice assembly, cyclic-reduction levels, back substitution
+// and pressure update, then the correction.  The step size is computed on the device
 // from the CFL ratio of the previous state, as in the SME step.
 #include <hip/hip_runtime.h>
 
@@ -14,6 +14,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "../../include/sme.h"
 #include "sme_host.h"
@@ -30,7 +31,9 @@ struct sme_vam {
     double *q[2] = {nullptr, nullptr};  // caller-owned
     int cur = 0;
     double *b = nullptr, *p = nullptr, *sys = nullptr;
-    VamSystem m[2]{};
+    std::vector<VamSystem> lev;   // reduction levels: lev[0] the assembled system
+    std::vector<int> nlev;        // equations per level
+    std::vector<double *> xlev;   // unknowns per level [4][n_l]
     Slot *slots = nullptr;
     ErrWord *err = nullptr;
     int sa = 0;
@@ -79,7 +82,22 @@ int valloc(sme_vam *c, T **p, size_t count)
     return SME_OK;
 }
 
-size_t system_doubles(int nb) { return (size_t)52 * (size_t)nb; }  // A, B, C (16 each) and d (4) per block
+// equations of the reduction levels: nb, nb / 2, ... down to one
+std::vector<int> level_sizes(int nb)
+{
+    std::vector<int> n{nb};
+    while (n.back() > 1) n.push_back(n.back() / 2);
+    return n;
+}
+
+// doubles of the block systems (A, B, C: 16 each, d: 4 per equation) and of
+// the unknowns (4 per equation) of every level
+size_t system_doubles(int nb)
+{
+    size_t t = 0;
+    for (int n : level_sizes(nb)) t += (size_t)56 * n;
+    return t;
+}
 
 VamArgs make_args(const sme_vam *c, double t_end, double dt_fixed)
 {
@@ -132,14 +150,13 @@ int queue_step(sme_vam *c, double t_end, double dt_fixed)
     VCHK(c, launch_vam_predict(a, c->stream));
     // Newton on the affine constraints: the first solve from P = 0, then one
     // more with the residual at the pressure found (see k_vam.hip)
+    const int L = (int)c->lev.size();
     for (int it = 0; it < kNewtonSolves; ++it) {
-        VCHK(c, launch_vam_assemble(a, c->m[0], it ? c->p : nullptr, c->stream));
-        int src = 0;
-        for (int s = 1; s < c->nb; s *= 2) {
-            VCHK(c, launch_vam_pcr(a, c->m[src], c->m[1 - src], s, c->stream));
-            src = 1 - src;
-        }
-        VCHK(c, launch_vam_solve(a, c->m[src], it, c->stream));
+        VCHK(c, launch_vam_assemble(a, c->lev[0], it ? c->p : nullptr, c->stream));
+        for (int l = 0; l + 1 < L; ++l) VCHK(c, launch_vam_reduce(c->nlev[l], c->lev[l], c->lev[l + 1], c->stream));
+        for (int l = L - 1; l >= 0; --l)
+            VCHK(c, launch_vam_back(c->nlev[l], c->lev[l], l + 1 < L ? c->xlev[l + 1] : nullptr, c->xlev[l], c->stream));
+        VCHK(c, launch_vam_scatter(a, c->xlev[0], it, c->stream));
     }
     VCHK(c, launch_vam_correct(a, c->stream));
     c->cur = 1 - c->cur;
@@ -172,7 +189,7 @@ int sme_vam_workspace_size(int64_t nx, size_t *bytes)
     if (nx < 1 || nx > ((int64_t)1 << 30) || !bytes) return SME_EINVAL;
     const int64_t st = vam_stride(nx);
     const int nb = (int)((nx + 1) / 2);
-    *bytes = sizeof(double) * (size_t)(st + 2 * st + 2 * system_doubles(nb) + 2 * kMaxQuadVam) + 3 * sizeof(Slot) +
+    *bytes = sizeof(double) * (size_t)(st + 2 * st + system_doubles(nb) + 2 * kMaxQuadVam) + 3 * sizeof(Slot) +
              sizeof(ErrWord);
     return SME_OK;
 }
@@ -210,7 +227,7 @@ int sme_vam_init(sme_vam **out, int64_t nx, double x0, double x1, double g, doub
     rc = rc ? rc : valloc(c, &c->quad_dev, 2 * kMaxQuadVam);
     rc = rc ? rc : valloc(c, &c->b, c->stride);
     rc = rc ? rc : valloc(c, &c->p, 2 * c->stride);
-    rc = rc ? rc : valloc(c, &c->sys, 2 * system_doubles(c->nb));
+    rc = rc ? rc : valloc(c, &c->sys, system_doubles(c->nb));
     rc = rc ? rc : valloc(c, &c->slots, 3);
     rc = rc ? rc : valloc(c, &c->err, 1);
     if (!rc) {
@@ -221,13 +238,17 @@ int sme_vam_init(sme_vam **out, int64_t nx, double x0, double x1, double g, doub
             rc = vfail(c, SME_EHIP, "quadrature upload failed");
         c->quad.s = c->quad_dev;
         c->quad.w = c->quad_dev + kMaxQuadVam;
-        const size_t nb = (size_t)c->nb;
-        for (int k = 0; k < 2; ++k) {
-            double *base = c->sys + k * system_doubles(c->nb);
-            c->m[k].A = base;
-            c->m[k].B = base + 16 * nb;
-            c->m[k].C = base + 32 * nb;
-            c->m[k].d = base + 48 * nb;
+        c->nlev = level_sizes(c->nb);
+        double *base = c->sys;
+        for (int n : c->nlev) {
+            VamSystem m;
+            m.A = base;
+            m.B = base + 16 * (size_t)n;
+            m.C = base + 32 * (size_t)n;
+            m.d = base + 48 * (size_t)n;
+            c->lev.push_back(m);
+            c->xlev.push_back(base + 52 * (size_t)n);
+            base += 56 * (size_t)n;
         }
     }
     if (!rc) {

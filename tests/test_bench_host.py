@@ -41,3 +41,14 @@ def test_committed_workloads_are_known():
         if f.endswith(".json"):
             wl = f.split("_", 1)[1][:-5]
             assert wl in bench.WORKLOADS, f
+
+
+def test_vam_bytes_per_cell():
+    import bench
+
+    # one block (two cells): no reduction level, one back substitution of 64 doubles
+    two = bench.vam_bytes_per_cell(2)
+    assert two == (88 * 2 + 528 * 2 + 2 * 8 * (64 + 8) + 16 * 2 + 96 * 2) / 2
+    # large channels: the reduction moves about three system entries per block and level sum
+    big = bench.vam_bytes_per_cell(1 << 20)
+    assert 2000 < big < 3000
