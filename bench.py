@@ -556,7 +556,7 @@ def bench_vam(args, wl, torch, sme, workloads):
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": wl["name"], "cells": nx, "levels_of_reduction": max(0, ((nx + 1) // 2 - 1).bit_length())},
         "roofline": {"bound": "hbm", "achieved": alg / per_step_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": alg / per_step_s / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                     "frac": alg / per_step_s / 1e9 / HBM_PEAK_GBS, "traffic": load_traffic(args.workload, alg),
                      "kernel": "one VAM step (k_vam_predict, 2 x (k_vam_assemble, k_vam_cr_reduce and k_vam_cr_back "
                                "per level, k_vam_scatter), k_vam_correct)",
                      "alg_bytes_per_launch": alg, "avg_launch_us": per_step_s * 1e6,
