@@ -7,7 +7,8 @@
   against the oracle run alone;
 * the learned closure on a 2D grid: trained on 1D level-8 runs of the same
   spacing, level 1 + closure must cut the relative L1 error of (h, hu)
-  against level 8 (gain < 1, and within twice the plain level-1 error).
+  against level 8 (gain < 1, and within twice the plain level-1 error), at
+  512^2 and in the full 2048^2 configuration bench.py times.
 Metric per field: max |gpu - oracle| / max |oracle| <= 1e-10.
 """
 import sys
@@ -130,3 +131,30 @@ def test_closure_gain_on_2d_grid(sme):
     assert gain < 0.6
     assert errs["closure"] <= 2.0 * errs["plain"]
     mlp.close()
+
+
+def test_closure_full_2048_configuration(sme):
+    """The closure's full configuration as bench.py runs it: training on 64
+    level-8 1D runs of 1000 steps at the 2048-cell spacing, 15 epochs, then on
+    the 2048^2 periodic level-8 grid (200 level-8 steps fix the end time)
+    level 1 + closure through the fallback policy against plain level 1, both
+    measured against level 8 on every cell.  The closure must stay inside its
+    training box (no fallback) and cut the relative L1 error of (h, hu) below
+    plain level 1's."""
+    import argparse
+    import os
+
+    import torch
+
+    sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), ".."))
+    import bench
+
+    args = argparse.Namespace(closure_seeds=64, closure_steps=1000, closure_epochs=15, closure_ref_steps=200,
+                              closure_precision="fp16")
+    out, mlp = bench.closure_comparison(args, torch, sme, W, lambda m: print(m, flush=True))
+    mlp.close()
+    c = out["closure"]
+    assert c["fell_back_at"] is None and c["out_of_range_cell_steps"] == 0
+    assert out["within_error_budget"]
+    assert out["error_ratio_over_plain_level1"] < 1.0, out["error_ratio_over_plain_level1"]
+    assert c["t"] == out["plain_level1"]["t"] == out["t_end"]
