@@ -58,43 +58,49 @@ WORKLOADS = {
                       name="batch_512_grids_side64-512_levels1-4_walls"),
     "closure_2048": dict(gen="closure", args={}, kernel="k_closure_rates_mfma",
                          name="closure_level1_vs_level8_2048x2048_periodic"),
-    # the non-hydrostatic VAM channel: a step is the predictor, two Newton passes of the corrector
-    # (assembly, block cyclic reduction level by level, back substitution, pressure update) and the
-    # correction
+    # the non-hydrostatic VAM channel: a step is the predictor, the corrector's solve (assembly,
+    # block cyclic reduction level by level, back substitution, pressure update), its Newton step on
+    # the residual (on the stored factors) and the correction
     "vam_1d": dict(gen="vam", args=dict(n=1 << 20, L=1000.0), kernel="k_vam_cr_reduce",
                    name="vam_1d_channel_1048576_cells_bore_over_hump"),
 }
 
 
 def vam_bytes_per_cell(nx):
-    """Algorithmic bytes per cell of one VAM step: predictor (5 fields + b in,
-    5 out), two Newton passes of the corrector -- assembly (5 fields + b
-    (+ p) in, 52 FP64 block entries per pair of cells out), block cyclic
-    reduction (at stride s the nb / s equations still active are read once,
-    the nb / 2s updated ones written), back substitution (A, B, C, d and the
-    two known neighbour blocks in, the block out), pressure update (x in, p
-    out, + p in) -- and the correction (5 fields, p, b in; 4 fields out)."""
+    """Algorithmic bytes per cell of one VAM step (FP64 words x 8):
+    - predictor: 5 fields + b in, 5 out;
+    - assembly: 5 fields + b in, 52 block entries per pair of cells out;
+    - first solve, per reduction level of n equations: A, B, C, d of every
+      equation in, the factors E, F, g, B^-1 of the even ones (52 each) and
+      the next level (52 per odd one) out; the top equation: B, d in, its
+      factors and unknowns out;
+    - residual at the pressure found: 5 fields + b + p in, d out (2 per cell);
+    - second solve on the stored factors, per level: d in, B^-1 of the even
+      equations and A, C of the odd ones in, g of the even ones and d of the
+      next level out; the top: B^-1, d in, unknowns out;
+    - back substitution of each solve, per level: E, F, g of the even
+      equations and the unknowns of the level above in, the unknowns out;
+    - pressure updates: x in, p out (p also in the second time);
+    - correction: 5 fields, p, b in, 4 fields out.
+    The last levels (a few dozen equations) are counted like the others,
+    though they stay in LDS."""
     nb = (nx + 1) // 2
-    top = 1
-    while 2 * top - 1 < nb:
-        top *= 2
-    reduce_d = back_d = 0
-    s = 1
-    while s < top:
-        active = (nb + 1) // s if s > 1 else nb       # equations with (k + 1) % s == 0
-        updated = nb // (2 * s)
-        reduce_d += 52 * active + 52 * updated
-        s *= 2
-    s = top
-    while s >= 1:
-        back_d += 64 * ((nb + s) // (2 * s))
-        s //= 2
-    solve_bytes = 8 * (reduce_d + back_d) + 8 * (8 * nb)  # + scatter: x in, p out
+    sizes = [nb]
+    while sizes[-1] > 1:
+        sizes.append(sizes[-1] // 2)
+    full, rhs, back = 20 + 52 + 4, 20 + 4, 0
+    for n in sizes[:-1]:
+        ne, nd = (n + 1) // 2, n // 2
+        full += 52 * n + 52 * ne + 52 * nd
+        rhs += 4 * n + 16 * ne + 32 * nd + 4 * ne + 4 * nd
+        back += 36 * ne + 4 * nd + 4 * n
     predict = 11 * 8 * nx
-    assemble = (6 * 8 + 26 * 8) * nx + (8 * 8 + 26 * 8) * nx
-    newton_p = 2 * 8 * nx                                  # p read by the second pass's update
-    correct = (8 * 8 + 4 * 8) * nx
-    return (predict + assemble + 2 * solve_bytes + newton_p + correct) / nx
+    assemble = (6 + 26) * 8 * nx
+    residual = (8 + 2) * 8 * nx
+    scatter = (4 + 6) * 8 * nx
+    correct = (8 + 4) * 8 * nx
+    solves = 8 * (full + rhs + 2 * back)
+    return (predict + assemble + residual + scatter + correct + solves) / nx
 
 
 def source_hash():
@@ -557,8 +563,9 @@ def bench_vam(args, wl, torch, sme, workloads):
         "config": {"workload": wl["name"], "cells": nx, "levels_of_reduction": max(0, ((nx + 1) // 2 - 1).bit_length())},
         "roofline": {"bound": "hbm", "achieved": alg / per_step_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": alg / per_step_s / 1e9 / HBM_PEAK_GBS, "traffic": load_traffic(args.workload, alg),
-                     "kernel": "one VAM step (k_vam_predict, 2 x (k_vam_assemble, k_vam_cr_reduce and k_vam_cr_back "
-                               "per level, k_vam_scatter), k_vam_correct)",
+                     "kernel": "one VAM step (k_vam_predict; k_vam_assemble, k_vam_cr_reduce per level, k_vam_cr_tail, "
+                               "k_vam_cr_back per level, k_vam_scatter; k_vam_residual, k_vam_cr_rhs per level, "
+                               "k_vam_cr_tail, k_vam_cr_back per level, k_vam_scatter; k_vam_correct)",
                      "alg_bytes_per_launch": alg, "avg_launch_us": per_step_s * 1e6,
                      "launch_timing": "HIP events on the step stream around the K timed steps, / K (a launch here "
                                       "is one step's kernel sequence)",

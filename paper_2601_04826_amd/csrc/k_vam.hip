@@ -16,15 +16,18 @@
 //   assemble   each cell's two constraint rows as affine forms in the unknowns
 //              of its five-cell neighbourhood (pairs of cells form the 4 x 4
 //              blocks of a block-tridiagonal system);
-//   reduce     parallel cyclic reduction, ceil(log2(blocks)) launches, each
-//              block eliminating its neighbours at distance 1, 2, 4, ...;
-//   solve      the decoupled 4 x 4 blocks (Gauss-Jordan, partial pivoting);
-//   newton     assemble again with the right-hand side -R(Q**(P)) at the
-//              pressure found, reduce, solve, and add the increment: one Newton
-//              step on the affine constraints (the reduction loses digits on
-//              long channels -- a relative residual of 1e-6 at 2^20 cells --
-//              and one such step brings it to the rounding level of a direct
-//              solve);
+//   reduce     block cyclic reduction: each level factors its even
+//              equations once and folds them into its odd ones, which form
+//              the next level (one launch per level down to a few thousand
+//              equations, the rest and their back substitution in one
+//              workgroup);
+//   back       back substitution from the one-equation top level down;
+//   newton     the right-hand side -R(Q**(P)) at the pressure found,
+//              evaluated on the corrected state itself, carried through the
+//              stored factors (the matrix does not depend on P), back
+//              substitution, and the increment added: one step of iterative
+//              refinement, which takes the constraint residual from the
+//              reduction's rounding to that of the residual evaluation;
 //   correct    Q** in place, and the CFL ratio of the new state.
 #include <hip/hip_runtime.h>
 
@@ -254,9 +257,8 @@ __device__ __forceinline__ void hu1_aff(const VamArgs &a, const Nbhd &n, int i, 
     aff_add(x, 1, j - i, -dt * (hx + 6.0 * bx));
 }
 
-// rows of the constraints at cell i; right-hand side -R(Q**(P)) at the
-// pressure pcur (null: P = 0)
-__global__ __launch_bounds__(kBlock) void k_vam_assemble(VamArgs a, VamSystem m, const double *pcur)
+// rows of the constraints at cell i, right-hand side -R(Q**(0))
+__global__ __launch_bounds__(kBlock) void k_vam_assemble(VamArgs a, VamSystem m)
 {
     const int i = blockIdx.x * kBlock + threadIdx.x;
     const int ncell = 2 * a.nb;  // nx, or nx + 1 with one padding cell
@@ -342,21 +344,8 @@ __global__ __launch_bounds__(kBlock) void k_vam_assemble(VamArgs a, VamSystem m,
                 }
             }
         }
-        double v0 = R0.k, v1 = R1.k;
-        if (pcur) {
-#pragma unroll
-            for (int comp = 0; comp < 2; ++comp)
-#pragma unroll
-                for (int o = -2; o <= 2; ++o) {
-                    const int mc = i + o;
-                    if (mc < 0 || mc >= a.nx) continue;
-                    const double pv = pcur[comp * a.stride + mc];
-                    v0 = fma(R0.c[comp * 5 + o + 2], pv, v0);
-                    v1 = fma(R1.c[comp * 5 + o + 2], pv, v1);
-                }
-        }
-        dd[0] = -v0;
-        dd[1] = -v1;
+        dd[0] = -R0.k;
+        dd[1] = -R1.k;
     }
     const int nb = a.nb;
 #pragma unroll
@@ -373,54 +362,50 @@ __global__ __launch_bounds__(kBlock) void k_vam_assemble(VamArgs a, VamSystem m,
 }
 
 // ---- 4 x 4 block algebra (row-major, registers only: every index is static)
-__device__ __forceinline__ void load4(const double *M, int nb, int k, double *X)
+// X = M^-1 by the adjugate: the 2 x 2 minors of the top two rows (s) and of
+// the bottom two rows (c) give the determinant (Laplace expansion along the
+// top two rows) and every cofactor as a three-term sum.  About 100 FP64
+// operations with a dependency depth of about 17, against about 370 and 75
+// for Gauss-Jordan elimination with pivoting; the blocks of the corrector's
+// system are well conditioned (diagonal blocks of a discrete second-order
+// operator and their Schur complements), and the second Newton solve on the
+// residual corrects what the inverse's rounding leaves.
+__device__ __forceinline__ void inv4(const double *a, double *X)
 {
-#pragma unroll
-    for (int e = 0; e < 16; ++e) X[e] = M[e * nb + k];
-}
-
-__device__ __forceinline__ void store4(double *M, int nb, int k, const double *X)
-{
-#pragma unroll
-    for (int e = 0; e < 16; ++e) M[e * nb + k] = X[e];
-}
-
-// X = inverse of M by Gauss-Jordan elimination with partial pivoting
-__device__ __forceinline__ void inv4(const double *M, double *X)
-{
-    double a[4][8];
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int c = 0; c < 8; ++c) a[r][c] = c < 4 ? M[r * 4 + c] : (c - 4 == r ? 1.0 : 0.0);
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        // bring the largest |a[r][c]|, r >= c, to row c by compare-and-swap
-#pragma unroll
-        for (int r = c + 1; r < 4; ++r) {
-            const bool sw = fabs(a[r][c]) > fabs(a[c][c]);
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const double t = a[c][e];
-                a[c][e] = sw ? a[r][e] : t;
-                a[r][e] = sw ? t : a[r][e];
-            }
-        }
-        const double ip = 1.0 / a[c][c];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) a[c][e] *= ip;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            if (r == c) continue;
-            const double f = a[r][c];
-#pragma unroll
-            for (int e = 0; e < 8; ++e) a[r][e] = fma(-f, a[c][e], a[r][e]);
-        }
-    }
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) X[r * 4 + c] = a[r][c + 4];
+    auto m2 = [](double p, double q, double r, double t) { return fma(p, q, -(r * t)); };  // p q - r t
+    const double s0 = m2(a[0], a[5], a[4], a[1]);
+    const double s1 = m2(a[0], a[6], a[4], a[2]);
+    const double s2 = m2(a[0], a[7], a[4], a[3]);
+    const double s3 = m2(a[1], a[6], a[5], a[2]);
+    const double s4 = m2(a[1], a[7], a[5], a[3]);
+    const double s5 = m2(a[2], a[7], a[6], a[3]);
+    const double c5 = m2(a[10], a[15], a[14], a[11]);
+    const double c4 = m2(a[9], a[15], a[13], a[11]);
+    const double c3 = m2(a[9], a[14], a[13], a[10]);
+    const double c2 = m2(a[8], a[15], a[12], a[11]);
+    const double c1 = m2(a[8], a[14], a[12], a[10]);
+    const double c0 = m2(a[8], a[13], a[12], a[9]);
+    const double det = fma(s0, c5, fma(-s1, c4, s2 * c3)) + fma(s3, c2, fma(-s4, c1, s5 * c0));
+    const double r = rcp(det);
+    auto e3 = [r](double x0, double y0, double x1, double y1, double x2, double y2) {
+        return r * fma(x0, y0, fma(x1, y1, x2 * y2));
+    };
+    X[0] = e3(a[5], c5, -a[6], c4, a[7], c3);
+    X[1] = e3(-a[1], c5, a[2], c4, -a[3], c3);
+    X[2] = e3(a[13], s5, -a[14], s4, a[15], s3);
+    X[3] = e3(-a[9], s5, a[10], s4, -a[11], s3);
+    X[4] = e3(-a[4], c5, a[6], c2, -a[7], c1);
+    X[5] = e3(a[0], c5, -a[2], c2, a[3], c1);
+    X[6] = e3(-a[12], s5, a[14], s2, -a[15], s1);
+    X[7] = e3(a[8], s5, -a[10], s2, a[11], s1);
+    X[8] = e3(a[4], c4, -a[5], c2, a[7], c0);
+    X[9] = e3(-a[0], c4, a[1], c2, -a[3], c0);
+    X[10] = e3(a[12], s4, -a[13], s2, a[15], s0);
+    X[11] = e3(-a[8], s4, a[9], s2, -a[11], s0);
+    X[12] = e3(-a[4], c3, a[5], c1, -a[6], c0);
+    X[13] = e3(a[0], c3, -a[1], c1, a[2], c0);
+    X[14] = e3(-a[12], s3, a[13], s1, -a[14], s0);
+    X[15] = e3(a[8], s3, -a[9], s1, a[10], s0);
 }
 
 // Z = X Y
@@ -437,8 +422,51 @@ __device__ __forceinline__ void mul4(const double *X, const double *Y, double *Z
         }
 }
 
-// Z += X Y
-__device__ __forceinline__ void muladd4(const double *X, const double *Y, double *Z)
+// Block cyclic reduction with the equations of every level stored apart and
+// contiguously.  Level l holds n_l equations A_j x_{j-1} + B_j x_j + C_j x_{j+1}
+// = d_j (no A for the first, no C for the last).  Every even equation i = 2u
+// is factored once:
+//   E_i = B_i^-1 A_i,  F_i = B_i^-1 C_i,  g_i = B_i^-1 d_i,
+// so that x_i = g_i - E_i x_{i-1} - F_i x_{i+1}.  Level l + 1 holds the odd
+// equations j = 2t + 1 with both even neighbours substituted, which couples
+// them to j -/+ 2 (equations t -/+ 1 of level l + 1):
+//   A' = -A_j E_{j-1},  C' = -C_j F_{j+1},  B' = B_j - A_j F_{j-1} - C_j E_{j+1},
+//   d' = d_j - A_j g_{j-1} - C_j g_{j+1}.
+// The top level's one equation is decoupled (x = g); back substitution then
+// visits the levels downwards: the odd unknowns of level l are those of level
+// l + 1, the even ones follow from their factors.  The factors, with B_i^-1,
+// are kept per level: a second solve with the same matrix and a new
+// right-hand side (the Newton step on the residual) only carries the
+// right-hand side down, g_i = B_i^-1 d_i and d' as above.
+// Every access is to consecutive equations (the compaction keeps the loads
+// coalesced at every level), and work and traffic halve from level to level.
+
+// a level's equations: entry e of equation j at A[e * s + j] (B, C: 16
+// entries, d: 4), in device memory or in LDS
+struct Eqs {
+    double *A, *B, *C, *d;
+    int s;
+};
+// factors of a level's even equations: entry e of even equation u at
+// f[e * s + u]; entries 0..15 E, 16..31 F, 32..35 g, 36..51 B^-1
+struct Facs {
+    double *f;
+    int s;
+};
+constexpr int kFacE = 0, kFacF = 16, kFacG = 32, kFacBi = 36, kFac = 52;
+
+__device__ __forceinline__ int evens(int n) { return (n + 1) / 2; }
+__device__ __forceinline__ Eqs eqs_of(const VamSystem &m, int n) { return Eqs{m.A, m.B, m.C, m.d, n}; }
+__device__ __forceinline__ Facs facs_of(const VamSystem &m, int n) { return Facs{m.fac, evens(n)}; }
+
+__device__ __forceinline__ void ld4(const Eqs &m, const double *M, int j, double *X)
+{
+#pragma unroll
+    for (int e = 0; e < 16; ++e) X[e] = M[e * m.s + j];
+}
+
+// Z -= X Y
+__device__ __forceinline__ void mulsub4(const double *X, const double *Y, double *Z)
 {
 #pragma unroll
     for (int r = 0; r < 4; ++r)
@@ -446,124 +474,413 @@ __device__ __forceinline__ void muladd4(const double *X, const double *Y, double
         for (int c = 0; c < 4; ++c) {
             double s = Z[r * 4 + c];
 #pragma unroll
-            for (int e = 0; e < 4; ++e) s = fma(X[r * 4 + e], Y[e * 4 + c], s);
+            for (int e = 0; e < 4; ++e) s = fma(-X[r * 4 + e], Y[e * 4 + c], s);
             Z[r * 4 + c] = s;
         }
 }
 
-// Block cyclic reduction with the equations of every level stored apart and
-// contiguously.  Level l holds n_l equations, equation j coupled to j - 1 and
-// j + 1 of the same level.  Level l + 1 holds the odd equations of level l,
-// j = 2t + 1, each updated by eliminating its couplings with the equations
-// j - 1 and j + 1 (which then couple it to j -/+ 2, the equations t -/+ 1 of
-// level l + 1):
-//   a = -A_j B_{j-1}^-1,  g = -C_j B_{j+1}^-1,
-//   A' = a A_{j-1},  C' = g C_{j+1},  B' = B_j + a C_{j-1} + g A_{j+1},
-//   d' = d_j + a d_{j-1} + g d_{j+1};
-// an equation without a right neighbour has no coupling to it.  The one
-// equation of the top level is decoupled; back substitution then visits the
-// levels downwards: the odd unknowns of level l are those of level l + 1, the
-// even ones follow from x_j = B_j^-1 (d_j - A_j x_{j-1} - C_j x_{j+1}).
-// Every access is to consecutive equations (the compaction keeps the loads
-// coalesced at every level), and work and traffic halve from level to level.
-__global__ __launch_bounds__(kBlock) void k_vam_cr_reduce(int n, VamSystem src, VamSystem dst)
+// factors of the even equation 2u of a level of n; the first equation has no
+// A (E = 0) and, for odd n, the last no C (F = 0)
+__device__ __forceinline__ void factor_even(int n, const Eqs &m, int u, double *E, double *F, double *g, double *Bi)
 {
-    const int t = blockIdx.x * kBlock + threadIdx.x;
-    const int nd = n / 2;
-    if (t >= nd) return;
-    const int j = 2 * t + 1;
-    double Bj[16], dj[4], T[16], G[16], Z[16];
-    load4(src.B, n, j, Bj);
-#pragma unroll
-    for (int r = 0; r < 4; ++r) dj[r] = src.d[r * n + j];
-    {
-        load4(src.B, n, j - 1, T);
-        inv4(T, Z);                    // B_{j-1}^-1
-        load4(src.A, n, j, T);
-        mul4(T, Z, G);                 // A_j B_{j-1}^-1
-#pragma unroll
-        for (int e = 0; e < 16; ++e) G[e] = -G[e];
-        load4(src.A, n, j - 1, T);
-        mul4(G, T, Z);
-        store4(dst.A, nd, t, Z);
-        load4(src.C, n, j - 1, T);
-        muladd4(G, T, Bj);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            double acc = dj[r];
-#pragma unroll
-            for (int e = 0; e < 4; ++e) acc = fma(G[r * 4 + e], src.d[e * n + j - 1], acc);
-            dj[r] = acc;
-        }
-    }
-    if (j + 1 < n) {
-        load4(src.B, n, j + 1, T);
-        inv4(T, Z);                    // B_{j+1}^-1
-        load4(src.C, n, j, T);
-        mul4(T, Z, G);                 // C_j B_{j+1}^-1
-#pragma unroll
-        for (int e = 0; e < 16; ++e) G[e] = -G[e];
-        load4(src.C, n, j + 1, T);
-        mul4(G, T, Z);
-        store4(dst.C, nd, t, Z);
-        load4(src.A, n, j + 1, T);
-        muladd4(G, T, Bj);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            double acc = dj[r];
-#pragma unroll
-            for (int e = 0; e < 4; ++e) acc = fma(G[r * 4 + e], src.d[e * n + j + 1], acc);
-            dj[r] = acc;
-        }
+    const int i = 2 * u;
+    double T[16];
+    ld4(m, m.B, i, T);
+    inv4(T, Bi);
+    if (i >= 1) {
+        ld4(m, m.A, i, T);
+        mul4(Bi, T, E);
     } else {
 #pragma unroll
-        for (int e = 0; e < 16; ++e) Z[e] = 0.0;
-        store4(dst.C, nd, t, Z);
+        for (int e = 0; e < 16; ++e) E[e] = 0.0;
     }
-    store4(dst.B, nd, t, Bj);
+    if (i + 1 < n) {
+        ld4(m, m.C, i, T);
+        mul4(Bi, T, F);
+    } else {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) dst.d[r * nd + t] = dj[r];
-}
-
-// back substitution of level l (n equations) into x ([4][n]); xup holds the
-// unknowns of level l + 1 (null at the top level, which has one equation)
-__global__ __launch_bounds__(kBlock) void k_vam_cr_back(int n, VamSystem m, const double *xup, double *x)
-{
-    const int j = blockIdx.x * kBlock + threadIdx.x;
-    if (j >= n) return;
-    const int nu = n / 2;
-    if (j & 1) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) x[r * n + j] = xup[r * nu + (j >> 1)];
-        return;
+        for (int e = 0; e < 16; ++e) F[e] = 0.0;
     }
-    double rhs[4], T[16], Z[16];
+    double d[4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) rhs[r] = m.d[r * n + j];
-    if (j >= 1) {
-        load4(m.A, n, j, T);
-        const int u = (j - 1) >> 1;  // x_{j-1} is unknown u of level l + 1
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) rhs[r] = fma(-T[r * 4 + e], xup[e * nu + u], rhs[r]);
-    }
-    if (j + 1 < n) {
-        load4(m.C, n, j, T);
-        const int u = j >> 1;        // x_{j+1}
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) rhs[r] = fma(-T[r * 4 + e], xup[e * nu + u], rhs[r]);
-    }
-    load4(m.B, n, j, T);
-    inv4(T, Z);
+    for (int r = 0; r < 4; ++r) d[r] = m.d[r * m.s + i];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         double v = 0.0;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) v = fma(Z[r * 4 + e], rhs[e], v);
-        x[r * n + j] = v;
+        for (int e = 0; e < 4; ++e) v = fma(Bi[r * 4 + e], d[e], v);
+        g[r] = v;
+    }
+}
+
+__device__ __forceinline__ void store_factors(const Facs &f, int u, const double *E, const double *F, const double *g,
+                                              const double *Bi)
+{
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        f.f[(kFacE + e) * f.s + u] = E[e];
+        f.f[(kFacF + e) * f.s + u] = F[e];
+        f.f[(kFacBi + e) * f.s + u] = Bi[e];
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) f.f[(kFacG + r) * f.s + u] = g[r];
+}
+
+// The odd equation j = 2t + 1 of a level of n (src; its A_j, B_j, d_j
+// already loaded) into equation t of the next level (dst); the factors of
+// j - 1 at fm[e * sm] and of j + 1 at fp[e * sp] (read only if j + 1 < n).
+__device__ __forceinline__ void reduce_odd(int n, const Eqs &src, const Eqs &dst, int t, const double *Aj,
+                                           double *Bj, double *dj, const double *fm, int sm, const double *fp, int sp)
+{
+    const int j = 2 * t + 1;
+    double M[16], X[16], Y[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) X[e] = fm[(kFacE + e) * sm];
+    mul4(Aj, X, Y);
+#pragma unroll
+    for (int e = 0; e < 16; ++e) dst.A[e * dst.s + t] = -Y[e];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) X[e] = fm[(kFacF + e) * sm];
+    mulsub4(Aj, X, Bj);
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) dj[r] = fma(-Aj[r * 4 + e], fm[(kFacG + e) * sm], dj[r]);
+    if (j + 1 < n) {
+        ld4(src, src.C, j, M);
+#pragma unroll
+        for (int e = 0; e < 16; ++e) X[e] = fp[(kFacE + e) * sp];
+        mulsub4(M, X, Bj);
+#pragma unroll
+        for (int e = 0; e < 16; ++e) X[e] = fp[(kFacF + e) * sp];
+        mul4(M, X, Y);
+#pragma unroll
+        for (int e = 0; e < 16; ++e) Y[e] = -Y[e];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) dj[r] = fma(-M[r * 4 + e], fp[(kFacG + e) * sp], dj[r]);
+    } else {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) Y[e] = 0.0;
+    }
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        dst.C[e * dst.s + t] = Y[e];
+        dst.B[e * dst.s + t] = Bj[e];
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) dst.d[r * dst.s + t] = dj[r];
+}
+
+__device__ __forceinline__ void load_odd(const Eqs &m, int j, double *Aj, double *Bj, double *dj)
+{
+    ld4(m, m.A, j, Aj);
+    ld4(m, m.B, j, Bj);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) dj[r] = m.d[r * m.s + j];
+}
+
+// g of the even equation 2u from its stored B^-1 and the level's new d
+__device__ __forceinline__ void g_even(const Eqs &m, const Facs &f, int u, double *g)
+{
+    double d[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) d[r] = m.d[r * m.s + 2 * u];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        double v = 0.0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v = fma(f.f[(kFacBi + r * 4 + e) * f.s + u], d[e], v);
+        g[r] = v;
+    }
+}
+
+// d of equation t of the next level for a new right-hand side; gm, gp the g
+// of the even neighbours 2t and 2t + 2, entry e at gm[e * sg] (gp read only
+// if 2t + 2 < n)
+__device__ __forceinline__ void rhs_odd(int n, const Eqs &src, const Eqs &dst, int t, const double *gm, int sg,
+                                        const double *gp)
+{
+    const int j = 2 * t + 1;
+    double dj[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) dj[r] = src.d[r * src.s + j];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) dj[r] = fma(-src.A[(r * 4 + e) * src.s + j], gm[e * sg], dj[r]);
+    if (j + 1 < n) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) dj[r] = fma(-src.C[(r * 4 + e) * src.s + j], gp[e * sg], dj[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) dst.d[r * dst.s + t] = dj[r];
+}
+
+// unknowns x_j of a level of n (entry r at x[r * sx + j]) from its factors
+// and the unknowns of the level above (xup[r * su + (j >> 1)])
+__device__ __forceinline__ void back_one(int n, const Facs &f, const double *xup, int su, double *x, int sx, int j)
+{
+    if (j & 1) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) x[r * sx + j] = xup[r * su + (j >> 1)];
+        return;
+    }
+    const int u = j >> 1;
+    double v[4], xs[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) v[r] = f.f[(kFacG + r) * f.s + u];
+    if (j >= 1) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) xs[e] = xup[e * su + ((j - 1) >> 1)];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) v[r] = fma(-f.f[(kFacE + r * 4 + e) * f.s + u], xs[e], v[r]);
+    }
+    if (j + 1 < n) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) xs[e] = xup[e * su + (j >> 1)];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) v[r] = fma(-f.f[(kFacF + r * 4 + e) * f.s + u], xs[e], v[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) x[r * sx + j] = v[r];
+}
+
+// A workgroup barrier that orders LDS only: the device-memory stores issued
+// before it are not waited for (a plain barrier would wait for all of them).
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// One level of the reduction.  A workgroup factors kRedThreads consecutive
+// even equations (into LDS, and into the level's factors) and then reduces
+// the kRedThreads - 1 odd equations between them; the last even equation of
+// a workgroup is the first of the next one, which alone stores it (if there
+// is a next one).  The odd equation's loads are issued before the even one's
+// arithmetic, so a level costs one round trip to memory.
+constexpr int kRedThreads = 256;
+
+__global__ __launch_bounds__(kRedThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_vam_cr_reduce(int n, VamSystem src, VamSystem dst)
+{
+    __shared__ double f[(kFacG + 4) * kRedThreads];  // E, F, g of the workgroup's even equations
+    const Eqs se = eqs_of(src, n), de = eqs_of(dst, n / 2);
+    const int ne = evens(n), nd = n / 2;
+    const int k = threadIdx.x;
+    const int u = blockIdx.x * (kRedThreads - 1) + k;
+    const bool odd = k < kRedThreads - 1 && u < nd;
+    double Aj[16], Bj[16], dj[4];
+    if (odd) load_odd(se, 2 * u + 1, Aj, Bj, dj);
+    if (u < ne) {
+        double E[16], F[16], g[4], Bi[16];
+        factor_even(n, se, u, E, F, g, Bi);
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            f[(kFacE + e) * kRedThreads + k] = E[e];
+            f[(kFacF + e) * kRedThreads + k] = F[e];
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) f[(kFacG + r) * kRedThreads + k] = g[r];
+        // the last one is stored by the next workgroup, if there is one
+        if (k < kRedThreads - 1 || (int)(blockIdx.x + 1) * (kRedThreads - 1) >= nd)
+            store_factors(facs_of(src, n), u, E, F, g, Bi);
+    }
+    lds_barrier();
+    if (odd) reduce_odd(n, se, de, u, Aj, Bj, dj, f + k, kRedThreads, f + k + 1, kRedThreads);
+}
+
+// The same level for a new right-hand side of the factored matrix.  Thread
+// t: g of the even equations 2t (stored) and 2t + 2 (stored only if it is
+// the last), then d of the next level's equation t.
+__global__ __launch_bounds__(kBlock) void k_vam_cr_rhs(int n, VamSystem src, VamSystem dst)
+{
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t >= n / 2) return;
+    const Eqs se = eqs_of(src, n), de = eqs_of(dst, n / 2);
+    const Facs fs = facs_of(src, n);
+    double gm[4], gp[4];
+    g_even(se, fs, t, gm);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) fs.f[(kFacG + r) * fs.s + t] = gm[r];
+    if (2 * t + 2 < n) {
+        g_even(se, fs, t + 1, gp);
+        if (t + 2 == fs.s) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) fs.f[(kFacG + r) * fs.s + t + 1] = gp[r];
+        }
+    }
+    rhs_odd(n, se, de, t, gm, 1, gp);
+}
+
+// back substitution of level l (n > 1 equations) into x ([4][n]) from the
+// unknowns xup of level l + 1
+__global__ __launch_bounds__(kBlock) void k_vam_cr_back(int n, VamSystem m, const double *xup, double *x)
+{
+    const int j = blockIdx.x * kBlock + threadIdx.x;
+    if (j < n) back_one(n, facs_of(m, n), xup, n / 2, x, n, j);
+}
+
+// The last levels of the reduction (at most kTailMax equations), the top
+// equation and the back substitution of those levels in one wave, with every
+// level in LDS: below a few hundred equations a level is too small to fill
+// the chip, and its cost is a launch and the latency of memory round trips
+// (about 2 us each); here the tail's first level is read once, everything
+// after it stays in LDS, and the unknowns of the first level are written
+// once.  The full solve also writes what a right-hand-side solve needs (the
+// tail levels' A and C and the factors) to device memory; the
+// right-hand-side solve (RHS) reads them back in one round trip.
+// Device memory as such: a pointer read from memory (here from the tail's
+// description) is generic to the compiler, and a generic access may alias
+// LDS, so it would be kept in order with every LDS access and never batched.
+typedef __attribute__((address_space(1))) double gdouble;
+__device__ __forceinline__ const gdouble *gptr(const double *p) { return (const gdouble *)p; }
+__device__ __forceinline__ gdouble *gptr(double *p) { return (gdouble *)p; }
+
+constexpr int kTailEq = 2 * kTailMax;   // equations of all tail levels, padded
+constexpr int kTailEv = kTailMax;       // even equations of all tail levels
+static_assert(kTailThreads == kWave, "the tail runs in one wave");
+
+template <bool RHS>
+__global__ __launch_bounds__(kTailThreads) void k_vam_cr_tail(const VamTail *tail)
+{
+    __shared__ double sA[16 * kTailEq], sB[16 * kTailEq], sC[16 * kTailEq], sd[4 * kTailEq], sx[4 * kTailEq];
+    __shared__ double sf[kFac * kTailEv];
+    __shared__ int eq[kTailLevels], ev[kTailLevels];  // level i's first equation and first even equation
+    const VamTail &lv = *tail;
+    const int top = lv.count - 1, tid = threadIdx.x;
+    if (tid == 0) {
+        eq[0] = ev[0] = 0;
+        for (int i = 1; i <= top; ++i) {
+            eq[i] = eq[i - 1] + lv.n[i - 1];
+            ev[i] = ev[i - 1] + evens(lv.n[i - 1]);
+        }
+    }
+    lds_barrier();
+    auto leqs = [&](int i) { return Eqs{sA + eq[i], sB + eq[i], sC + eq[i], sd + eq[i], kTailEq}; };
+    auto lfacs = [&](int i) { return Facs{sf + ev[i], kTailEv}; };
+    const int n0 = lv.n[0];
+    if constexpr (!RHS) {
+        const Eqs g0 = eqs_of(lv.m[0], n0);
+        for (int j = tid; j < n0; j += kTailThreads) {
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                sA[e * kTailEq + j] = gptr(g0.A)[e * n0 + j];
+                sB[e * kTailEq + j] = gptr(g0.B)[e * n0 + j];
+                sC[e * kTailEq + j] = gptr(g0.C)[e * n0 + j];
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) sd[r * kTailEq + j] = gptr(g0.d)[r * n0 + j];
+        }
+    } else {
+        for (int i = 0; i <= top; ++i) {
+            const int n = lv.n[i];
+            const Eqs g = eqs_of(lv.m[i], n);
+            const Facs gf = facs_of(lv.m[i], n);
+            for (int j = tid; j < n; j += kTailThreads) {
+#pragma unroll
+                for (int e = 0; e < 16; ++e) {
+                    sA[e * kTailEq + eq[i] + j] = gptr(g.A)[e * n + j];
+                    sC[e * kTailEq + eq[i] + j] = gptr(g.C)[e * n + j];
+                }
+                if (i == 0) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) sd[r * kTailEq + j] = gptr(g.d)[r * n + j];
+                }
+            }
+            for (int u = tid; u < gf.s; u += kTailThreads) {
+#pragma unroll
+                for (int e = 0; e < kFac; ++e) sf[e * kTailEv + ev[i] + u] = gptr(gf.f)[e * gf.s + u];
+            }
+        }
+    }
+    lds_barrier();
+    for (int i = 0; i < top; ++i) {
+        const int n = lv.n[i], ne = evens(n), nd = n / 2;
+        const Eqs se = leqs(i), de = leqs(i + 1);
+        const Facs sfi = lfacs(i);
+        if constexpr (RHS) {
+            for (int u = tid; u < ne; u += kTailThreads) {
+                double g[4];
+                g_even(se, sfi, u, g);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) sfi.f[(kFacG + r) * sfi.s + u] = g[r];
+            }
+            lds_barrier();
+            for (int t = tid; t < nd; t += kTailThreads)
+                rhs_odd(n, se, de, t, sfi.f + kFacG * sfi.s + t, sfi.s, sfi.f + kFacG * sfi.s + t + 1);
+        } else {
+            for (int u = tid; u < ne; u += kTailThreads) {
+                double E[16], F[16], g[4], Bi[16];
+                factor_even(n, se, u, E, F, g, Bi);
+                store_factors(sfi, u, E, F, g, Bi);
+            }
+            lds_barrier();
+            for (int t = tid; t < nd; t += kTailThreads) {
+                double Aj[16], Bj[16], dj[4];
+                load_odd(se, 2 * t + 1, Aj, Bj, dj);
+                reduce_odd(n, se, de, t, Aj, Bj, dj, sfi.f + t, sfi.s, sfi.f + t + 1, sfi.s);
+            }
+        }
+        lds_barrier();
+    }
+    if (tid == 0) {
+        const Eqs se = leqs(top);
+        const Facs sft = lfacs(top);
+        double g[4];
+        if constexpr (RHS) {
+            g_even(se, sft, 0, g);
+        } else {
+            double E[16], F[16], Bi[16];
+            factor_even(1, se, 0, E, F, g, Bi);
+            store_factors(sft, 0, E, F, g, Bi);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            sft.f[(kFacG + r) * sft.s] = g[r];
+            sx[r * kTailEq + eq[top]] = g[r];
+        }
+    }
+    lds_barrier();
+    for (int i = top - 1; i >= 0; --i) {
+        const int n = lv.n[i];
+        for (int j = tid; j < n; j += kTailThreads)
+            back_one(n, lfacs(i), sx + eq[i + 1], kTailEq, sx + eq[i], kTailEq, j);
+        lds_barrier();
+    }
+    for (int j = tid; j < n0; j += kTailThreads) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) gptr(lv.x[0])[r * n0 + j] = sx[r * kTailEq + j];
+    }
+    if constexpr (!RHS) {
+        // what a right-hand-side solve reads: A and C of every tail level
+        // after the first, the factors of every tail level
+        for (int i = 0; i <= top; ++i) {
+            const int n = lv.n[i];
+            const Eqs g = eqs_of(lv.m[i], n);
+            const Facs gf = facs_of(lv.m[i], n);
+            if (i > 0) {
+                for (int j = tid; j < n; j += kTailThreads) {
+#pragma unroll
+                    for (int e = 0; e < 16; ++e) {
+                        gptr(g.A)[e * n + j] = sA[e * kTailEq + eq[i] + j];
+                        gptr(g.C)[e * n + j] = sC[e * kTailEq + eq[i] + j];
+                    }
+                }
+            }
+            for (int u = tid; u < gf.s; u += kTailThreads) {
+#pragma unroll
+                for (int e = 0; e < kFac; ++e) gptr(gf.f)[e * gf.s + u] = sf[e * kTailEv + ev[i] + u];
+            }
+        }
     }
 }
 
@@ -579,6 +896,54 @@ __global__ __launch_bounds__(kBlock) void k_vam_scatter(VamArgs a, const double 
     a.p[a.stride + cell] = accumulate ? a.p[a.stride + cell] + x1 : x1;
 }
 
+// Q** = Q* + dt S^P(Q*, P) at cell i (v holds Q* on entry); P at p[c * stride + cell]
+__device__ __forceinline__ void corrected(const VamArgs &a, const double *p, int i, double dt, double *v)
+{
+    const int im = clampi(i - 1, a.nx), ip = clampi(i + 1, a.nx);
+    const double inv2dx = 0.5 / a.dx;
+    const double hm = a.qs[im], hp = a.qs[ip];
+    const double hx = (hp - hm) * inv2dx, bx = (a.b[ip] - a.b[im]) * inv2dx;
+    const double p0 = p[i], p1 = p[a.stride + i];
+    const double dhp0 = (hp * p[ip] - hm * p[im]) * inv2dx;
+    const double dhp1 = (hp * p[a.stride + ip] - hm * p[a.stride + im]) * inv2dx;
+    v[1] = v[1] - dt * (dhp0 + 2.0 * p1 * bx);
+    v[2] = v[2] - dt * (dhp1 - (3.0 * p0 - p1) * hx - 6.0 * (p0 - p1) * bx);
+    v[3] = v[3] + dt * (2.0 * p1);
+    v[4] = v[4] - dt * (6.0 * (p0 - p1));
+}
+
+// right-hand side -R(Q**(P)) of cell i's two constraint rows at the pressure
+// P = a.p, from the corrected state itself (Q** at i - 1, i, i + 1): the
+// Newton step's residual, for the matrix factored by the first solve
+__global__ __launch_bounds__(kBlock) void k_vam_residual(VamArgs a, VamSystem m)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    const int ncell = 2 * a.nb;
+    if (i >= ncell) return;
+    const double dt = a.slots[a.sb].dt;
+    double R0 = 0.0, R1 = 0.0;
+    if (i < a.nx && dt != 0.0) {
+        const int im = clampi(i - 1, a.nx), ip = clampi(i + 1, a.nx);
+        const double inv2dx = 0.5 / a.dx;
+        double vm[5], v[5], vp[5];
+        load_cell(a.qs, a.stride, im, vm);
+        load_cell(a.qs, a.stride, i, v);
+        load_cell(a.qs, a.stride, ip, vp);
+        corrected(a, a.p, im, dt, vm);
+        corrected(a, a.p, i, dt, v);
+        corrected(a, a.p, ip, dt, vp);
+        const double h = v[0], ih = 1.0 / h;
+        const double hx = (vp[0] - vm[0]) * inv2dx, bx = (a.b[ip] - a.b[im]) * inv2dx;
+        const double u0x = (vp[1] / vp[0] - vm[1] / vm[0]) * inv2dx;
+        const double u0 = v[1] * ih, u1 = v[2] * ih, w0 = v[3] * ih, w1 = v[4] * ih;
+        R0 = h * u0x + (vp[2] - vm[2]) * inv2dx / 3.0 + u1 * hx / 3.0 + 2.0 * (w0 - u0 * bx);
+        R1 = h * u0x + u1 * hx + 2.0 * (u1 * bx - w1);
+    }
+    const int k = i >> 1, r0 = 2 * (i & 1);
+    m.d[r0 * a.nb + k] = -R0;
+    m.d[(r0 + 1) * a.nb + k] = -R1;
+}
+
 __global__ __launch_bounds__(kBlock) void k_vam_correct(VamArgs a)
 {
     const double dt = a.slots[a.sb].dt;
@@ -586,20 +951,10 @@ __global__ __launch_bounds__(kBlock) void k_vam_correct(VamArgs a)
     const int i = blockIdx.x * kBlock + threadIdx.x;
     double r = 0.0;
     if (i < a.nx) {
-        const int im = clampi(i - 1, a.nx), ip = clampi(i + 1, a.nx);
         double v[5];
         load_cell(a.qs, a.stride, i, v);
         if (dt != 0.0) {
-            const double inv2dx = 0.5 / a.dx;
-            const double hm = a.qs[im], hp = a.qs[ip];
-            const double hx = (hp - hm) * inv2dx, bx = (a.b[ip] - a.b[im]) * inv2dx;
-            const double p0 = a.p[i], p1 = a.p[a.stride + i];
-            const double dhp0 = (hp * a.p[ip] - hm * a.p[im]) * inv2dx;
-            const double dhp1 = (hp * a.p[a.stride + ip] - hm * a.p[a.stride + im]) * inv2dx;
-            v[1] = v[1] - dt * (dhp0 + 2.0 * p1 * bx);
-            v[2] = v[2] - dt * (dhp1 - (3.0 * p0 - p1) * hx - 6.0 * (p0 - p1) * bx);
-            v[3] = v[3] + dt * (2.0 * p1);
-            v[4] = v[4] - dt * (6.0 * (p0 - p1));
+            corrected(a, a.p, i, dt, v);
 #pragma unroll
             for (int f = 1; f < 5; ++f) a.qs[f * a.stride + i] = v[f];
         }
@@ -628,22 +983,42 @@ hipError_t launch_vam_predict(const VamArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_vam_assemble(const VamArgs &a, const VamSystem &m, const double *pcur, hipStream_t s)
+hipError_t launch_vam_assemble(const VamArgs &a, const VamSystem &m, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_vam_assemble, dim3(blocks_for(2 * (int64_t)a.nb)), dim3(kBlock), 0, s, a, m, pcur);
+    hipLaunchKernelGGL(k_vam_assemble, dim3(blocks_for(2 * (int64_t)a.nb)), dim3(kBlock), 0, s, a, m);
     return hipGetLastError();
 }
 
-hipError_t launch_vam_reduce(int n, const VamSystem &src, const VamSystem &dst, hipStream_t s)
+hipError_t launch_vam_residual(const VamArgs &a, const VamSystem &m, hipStream_t s)
 {
-    if (n / 2 == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_vam_cr_reduce, dim3(blocks_for(n / 2)), dim3(kBlock), 0, s, n, src, dst);
+    hipLaunchKernelGGL(k_vam_residual, dim3(blocks_for(2 * (int64_t)a.nb)), dim3(kBlock), 0, s, a, m);
+    return hipGetLastError();
+}
+
+hipError_t launch_vam_reduce(int n, const VamSystem &src, const VamSystem &dst, bool rhs_only, hipStream_t s)
+{
+    const int nd = n / 2;
+    if (nd == 0) return hipSuccess;
+    if (rhs_only)
+        hipLaunchKernelGGL(k_vam_cr_rhs, dim3(blocks_for(nd)), dim3(kBlock), 0, s, n, src, dst);
+    else
+        hipLaunchKernelGGL(k_vam_cr_reduce, dim3((nd + kRedThreads - 2) / (kRedThreads - 1)), dim3(kRedThreads), 0, s,
+                           n, src, dst);
     return hipGetLastError();
 }
 
 hipError_t launch_vam_back(int n, const VamSystem &m, const double *xup, double *x, hipStream_t s)
 {
     hipLaunchKernelGGL(k_vam_cr_back, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, m, xup, x);
+    return hipGetLastError();
+}
+
+hipError_t launch_vam_tail(const VamTail *lv_dev, bool rhs_only, hipStream_t s)
+{
+    if (rhs_only)
+        hipLaunchKernelGGL(k_vam_cr_tail<true>, dim3(1), dim3(kTailThreads), 0, s, lv_dev);
+    else
+        hipLaunchKernelGGL(k_vam_cr_tail<false>, dim3(1), dim3(kTailThreads), 0, s, lv_dev);
     return hipGetLastError();
 }
 

@@ -2,11 +2,13 @@
 // include/sme.h, kernels in k_vam.hip).
 //
 // Binds the caller's two state buffers, owns the bathymetry, the pressure,
-// the block-tridiagonal system of the corrector (reduced in place) and the
-// time slots, and queues the kernels of a step on the caller's stream:
-// predictor, then twice assembly, cyclic-reduction levels, back substitution
-// and pressure update, then the correction.  The step size is computed on the device
-// from the CFL ratio of the previous state, as in the SME step.
+// the block-tridiagonal system of the corrector with its reduction levels and
+// their factors, and the time slots, and queues the kernels of a step on the
+// caller's stream: predictor; assembly, reduction levels, back substitution
+// and pressure update; the residual at that pressure, the same levels for
+// the right-hand side alone, back substitution and pressure increment; then
+// the correction.  The step size is computed on the device from the CFL
+// ratio of the previous state, as in the SME step.
 #include <hip/hip_runtime.h>
 
 #include <cstdarg>
@@ -34,6 +36,8 @@ struct sme_vam {
     std::vector<VamSystem> lev;   // reduction levels: lev[0] the assembled system
     std::vector<int> nlev;        // equations per level
     std::vector<double *> xlev;   // unknowns per level [4][n_l]
+    int l0 = 0;                   // first level of the one-workgroup tail
+    VamTail *tail = nullptr;      // its description, in device memory
     Slot *slots = nullptr;
     ErrWord *err = nullptr;
     int sa = 0;
@@ -90,12 +94,13 @@ std::vector<int> level_sizes(int nb)
     return n;
 }
 
-// doubles of the block systems (A, B, C: 16 each, d: 4 per equation) and of
-// the unknowns (4 per equation) of every level
+// doubles of the block systems (A, B, C: 16 each, d: 4 per equation), of
+// the unknowns (4 per equation) and of the even equations' factors (52 per
+// even equation) of every level
 size_t system_doubles(int nb)
 {
     size_t t = 0;
-    for (int n : level_sizes(nb)) t += (size_t)56 * n;
+    for (int n : level_sizes(nb)) t += (size_t)56 * n + (size_t)52 * ((n + 1) / 2);
     return t;
 }
 
@@ -150,12 +155,17 @@ int queue_step(sme_vam *c, double t_end, double dt_fixed)
     VCHK(c, launch_vam_predict(a, c->stream));
     // Newton on the affine constraints: the first solve from P = 0, then one
     // more with the residual at the pressure found (see k_vam.hip)
-    const int L = (int)c->lev.size();
+    // levels [0, l0) by one launch each, levels [l0, L) by one wave in LDS
+    const int l0 = c->l0;
     for (int it = 0; it < kNewtonSolves; ++it) {
-        VCHK(c, launch_vam_assemble(a, c->lev[0], it ? c->p : nullptr, c->stream));
-        for (int l = 0; l + 1 < L; ++l) VCHK(c, launch_vam_reduce(c->nlev[l], c->lev[l], c->lev[l + 1], c->stream));
-        for (int l = L - 1; l >= 0; --l)
-            VCHK(c, launch_vam_back(c->nlev[l], c->lev[l], l + 1 < L ? c->xlev[l + 1] : nullptr, c->xlev[l], c->stream));
+        // the matrix does not depend on P: factored by the first solve, reused after
+        const bool rhs = it > 0;
+        VCHK(c, rhs ? launch_vam_residual(a, c->lev[0], c->stream) : launch_vam_assemble(a, c->lev[0], c->stream));
+        for (int l = 0; l < l0; ++l)
+            VCHK(c, launch_vam_reduce(c->nlev[l], c->lev[l], c->lev[l + 1], rhs, c->stream));
+        VCHK(c, launch_vam_tail(c->tail, rhs, c->stream));
+        for (int l = l0 - 1; l >= 0; --l)
+            VCHK(c, launch_vam_back(c->nlev[l], c->lev[l], c->xlev[l + 1], c->xlev[l], c->stream));
         VCHK(c, launch_vam_scatter(a, c->xlev[0], it, c->stream));
     }
     VCHK(c, launch_vam_correct(a, c->stream));
@@ -189,8 +199,8 @@ int sme_vam_workspace_size(int64_t nx, size_t *bytes)
     if (nx < 1 || nx > ((int64_t)1 << 30) || !bytes) return SME_EINVAL;
     const int64_t st = vam_stride(nx);
     const int nb = (int)((nx + 1) / 2);
-    *bytes = sizeof(double) * (size_t)(st + 2 * st + system_doubles(nb) + 2 * kMaxQuadVam) + 3 * sizeof(Slot) +
-             sizeof(ErrWord);
+    *bytes = sizeof(double) * (size_t)(st + 2 * st + system_doubles(nb) + 2 * kMaxQuadVam) + sizeof(VamTail) +
+             3 * sizeof(Slot) + sizeof(ErrWord);
     return SME_OK;
 }
 
@@ -228,6 +238,7 @@ int sme_vam_init(sme_vam **out, int64_t nx, double x0, double x1, double g, doub
     rc = rc ? rc : valloc(c, &c->b, c->stride);
     rc = rc ? rc : valloc(c, &c->p, 2 * c->stride);
     rc = rc ? rc : valloc(c, &c->sys, system_doubles(c->nb));
+    rc = rc ? rc : valloc(c, &c->tail, 1);
     rc = rc ? rc : valloc(c, &c->slots, 3);
     rc = rc ? rc : valloc(c, &c->err, 1);
     if (!rc) {
@@ -246,10 +257,22 @@ int sme_vam_init(sme_vam **out, int64_t nx, double x0, double x1, double g, doub
             m.B = base + 16 * (size_t)n;
             m.C = base + 32 * (size_t)n;
             m.d = base + 48 * (size_t)n;
+            m.fac = base + 56 * (size_t)n;
             c->lev.push_back(m);
             c->xlev.push_back(base + 52 * (size_t)n);
-            base += 56 * (size_t)n;
+            base += 56 * (size_t)n + 52 * (size_t)((n + 1) / 2);
         }
+        const int L = (int)c->nlev.size();
+        while (c->nlev[c->l0] > kTailMax) ++c->l0;
+        VamTail tail{};
+        tail.count = L - c->l0;
+        for (int l = c->l0; l < L; ++l) {
+            tail.m[l - c->l0] = c->lev[l];
+            tail.x[l - c->l0] = c->xlev[l];
+            tail.n[l - c->l0] = c->nlev[l];
+        }
+        if (!rc && hipMemcpy(c->tail, &tail, sizeof tail, hipMemcpyHostToDevice) != hipSuccess)
+            rc = vfail(c, SME_EHIP, "reduction tail upload failed");
     }
     if (!rc) {
         hipError_t e = hipMemsetAsync(c->b, 0, c->stride * sizeof(double), c->stream);
@@ -368,6 +391,7 @@ void sme_vam_destroy(sme_vam *c)
     (void)hipFree(c->b);
     (void)hipFree(c->p);
     (void)hipFree(c->sys);
+    (void)hipFree(c->tail);
     (void)hipFree(c->slots);
     (void)hipFree(c->err);
     delete c;

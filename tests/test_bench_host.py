@@ -46,9 +46,11 @@ def test_committed_workloads_are_known():
 def test_vam_bytes_per_cell():
     import bench
 
-    # one block (two cells): no reduction level, one back substitution of 64 doubles
+    # one block (two cells): no reduction level, only the top equation of each solve
     two = bench.vam_bytes_per_cell(2)
-    assert two == (88 * 2 + 528 * 2 + 2 * 8 * (64 + 8) + 16 * 2 + 96 * 2) / 2
-    # large channels: the reduction moves about three system entries per block and level sum
+    assert two == (88 * 2 + 256 * 2 + 80 * 2 + 80 * 2 + 96 * 2 + 8 * (76 + 24)) / 2
+    # a level of n equations: 104 n words in the first solve, 32 n in the
+    # second, 24 n per back substitution; the levels sum to about 2 nb = nx
     big = bench.vam_bytes_per_cell(1 << 20)
-    assert 2000 < big < 3000
+    per_cell = 88 + 256 + 80 + 80 + 96 + 8 * (104 + 32 + 2 * 24)
+    assert abs(big - per_cell) < 0.01 * per_cell

@@ -1,9 +1,10 @@
 """GPU parity of the non-hydrostatic VAM channel (sme_vam_*) against the oracle.
 
 The kernels assemble the corrector's constraint rows as affine forms and
-solve the block-tridiagonal system by parallel cyclic reduction; the oracle
-probes the same affine map numerically and solves with a sparse direct
-solver.  Metric as in the other parity tests: per field max |gpu - oracle| /
+solve the block-tridiagonal system by block cyclic reduction (each level's
+even blocks factored once, the factors reused by the Newton step on the
+residual); the oracle probes the same affine map numerically and solves with
+a sparse direct solver.  Metric as in the other parity tests: per field max |gpu - oracle| /
 max |oracle|.  The state after a step agrees to 1e-9 and the pressure to 1e-8
 of its largest value (both sides solve a linear system whose condition number
 grows like (h / dx)^2); CFL steps agree to 1e-12.
