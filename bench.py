@@ -42,6 +42,27 @@ def bytes_per_cell(kind, level):
     return b
 
 
+def bytes_per_cell_o2(kind, level):
+    """Second-order step on a 1D or structured grid, four launches: two
+    reconstructions (the state and b in, the slopes of the nf + 1
+    reconstruction variables per axis out), stage 1 (state, b and slopes in,
+    Q1 out) and stage 2 (Q1, b, slopes and Q^n in, the new state out)."""
+    nf = level + 2 if kind == "1d" else 2 * level + 3
+    axes = 1 if kind == "1d" else 2
+    slopes = axes * (nf + 1)
+    recon = (nf + 1) + slopes
+    stage1 = (nf + 1) + slopes + nf
+    stage2 = (nf + 1) + slopes + 2 * nf
+    return 8 * (2 * recon + stage1 + stage2)
+
+
+def lift_bytes_per_cell(kind, level, nz):
+    """3D lifting of a 1D or structured state: the state and b in, z, u, v,
+    w, p at nz sigma levels out."""
+    nf = level + 2 if kind == "1d" else 2 * level + 3
+    return 8 * (nf + 1) + 8 * 5 * nz
+
+
 WORKLOADS = {
     "struct_2d_1024_l2": dict(gen="struct_2d", args={}, kernel="k_step_2d", name="struct_2d_1024x1024_level2_periodic"),
     "tri_4m_l3": dict(gen="tri_2d", args={}, kernel="k_step_tri", name="tri_delaunay_4M_level3_walls"),
@@ -63,6 +84,18 @@ WORKLOADS = {
     # the residual (on the stored factors) and the correction
     "vam_1d": dict(gen="vam", args=dict(n=1 << 20, L=1000.0), kernel="k_vam_cr_reduce",
                    name="vam_1d_channel_1048576_cells_bore_over_hump"),
+    # the default grid with the friction step by backward Euler (cell-local solve)
+    "struct_2d_1024_l2_implicit": dict(gen="struct_2d", args=dict(params=dict(implicit_friction=1)),
+                                       kernel="k_step_2d",
+                                       name="struct_2d_1024x1024_level2_periodic_implicit_friction"),
+    # the default grid with the second-order scheme: a step is four launches
+    "struct_2d_1024_l2_o2": dict(gen="struct_2d", args=dict(params=dict(order=2)), kernel="k_flux2",
+                                 name="struct_2d_1024x1024_level2_periodic_second_order",
+                                 timing="HIP events on the step stream around the K timed steps, / K (a launch "
+                                        "here is one step: k_recon, k_flux2 stage 1, k_recon, k_flux2 stage 2)"),
+    # 3D lifting of a level-2 1024^2 state to 32 sigma levels
+    "lift_1024_l2": dict(gen="lift", args=dict(n=1024, level=2, nz=32), kernel="k_lift",
+                         name="lift_3d_1024x1024_level2_32_sigma_levels"),
 }
 
 
@@ -230,6 +263,8 @@ def main():
         return bench_closure(args, wl, torch, sme, workloads)
     if wl["gen"] == "vam":
         return bench_vam(args, wl, torch, sme, workloads)
+    if wl["gen"] == "lift":
+        return bench_lift(args, wl, torch, sme, workloads)
     t0 = time.perf_counter()
     problem = getattr(workloads, wl["gen"])(**wl["args"])
     print(f"[bench] workload {wl['name']}: {problem['ncells']} cells, level {problem['level']} "
@@ -268,12 +303,14 @@ def main():
     solver.close()
     print(f"[bench] {args.steps} steps in {ms:.3f} ms (events), {wall * 1e3:.3f} ms wall; "
           f"simulated t = {t_sim:.6g} s over {nsteps} steps", file=sys.stderr, flush=True)
-    copy_gbs = copy_rate(torch, stream, bytes_per_cell(problem["kind"], problem["level"]) * problem["ncells"])
+    order = problem["params"].get("order", 1)
+    bpc = (bytes_per_cell_o2 if order == 2 else bytes_per_cell)(problem["kind"], problem["level"])
+    copy_gbs = copy_rate(torch, stream, bpc * problem["ncells"])
 
     ncells = problem["ncells"]
     value = ncells * args.steps / (ms * 1e-3)
-    per_launch_s = ms * 1e-3 / args.steps  # one step kernel per step of the timed region
-    alg_bytes = bytes_per_cell(problem["kind"], problem["level"]) * ncells
+    per_launch_s = ms * 1e-3 / args.steps  # one step (one kernel, or the four of the second order) per step
+    alg_bytes = bpc * ncells
     achieved = alg_bytes / per_launch_s / 1e9
     traffic = load_traffic(args.workload, alg_bytes)
     out = {
@@ -290,7 +327,8 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": wl["name"], "cells": ncells, "level": problem["level"],
-                   "fields": problem["q"].shape[0], "cfl": problem["params"]["cfl"]},
+                   "fields": problem["q"].shape[0], "cfl": problem["params"]["cfl"], "order": order,
+                   "implicit_friction": int(problem["params"].get("implicit_friction", 0))},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": wl["kernel"], "alg_bytes_per_launch": alg_bytes,
@@ -530,6 +568,67 @@ def bench_batch(args, wl, torch, sme, workloads):
         out["cpu_baseline"] = dict(value=done / el, unit="cell-updates/s", cores=orc.max_threads(), kind="oracle",
                                    sample=f"one step of the first {done} cells of the ensemble ({el:.1f} s)")
     print(json.dumps(out), flush=True)
+
+
+def bench_lift(args, wl, torch, sme, workloads):
+    """3D lifting (interpolate_3d) of a structured level-N state to nz sigma
+    levels: K launches, each writing z, u, v, w, p of every cell and level."""
+    a = wl["args"]
+    p = workloads.struct_2d(n=a["n"], level=a["level"])
+    nz, ncells = a["nz"], p["ncells"]
+    zeta = np.linspace(0.0, 1.0, nz)
+    print(f"[bench] workload {wl['name']}: {ncells} cells, {nz} sigma levels", file=sys.stderr, flush=True)
+    stream = torch.cuda.Stream()
+    s = sme.Solver(p, stream=stream.cuda_stream)
+    s.set_state(torch.from_numpy(p["q"]).cuda())
+    s.run(20)  # a state with flow: every moment and gradient generic
+    out = torch.empty((5, nz, ncells), dtype=torch.float64, device="cuda")
+    for _ in range(args.warmup):
+        s.interpolate_3d_into(zeta, out)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(args.steps):
+        s.interpolate_3d_into(zeta, out)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    Q = s.get_state()
+    s.close()
+    per_launch_s = ms * 1e-3 / args.steps
+    alg = lift_bytes_per_cell("2d", p["level"], nz) * ncells
+    copy_gbs = copy_rate(torch, stream, alg)
+    out_ = {
+        "metric": "lifted cells/s (FP64, z u v w p at every sigma level)", "value": ncells * args.steps / (ms * 1e-3),
+        "unit": "cells/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms / args.steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": wl["name"], "cells": ncells, "level": p["level"], "sigma_levels": nz},
+        "roofline": {"bound": "hbm", "achieved": alg / per_launch_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": alg / per_launch_s / 1e9 / HBM_PEAK_GBS, "traffic": load_traffic(args.workload, alg),
+                     "kernel": wl["kernel"], "alg_bytes_per_launch": alg, "avg_launch_us": per_launch_s * 1e6,
+                     "launch_timing": "HIP events on the solver's stream around the K timed launches, / K",
+                     "copy_gbs_same_bytes": copy_gbs, "frac_of_copy": alg / per_launch_s / 1e9 / copy_gbs},
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        from oracle import lift as olift
+        from oracle import sme as orc
+
+        m = orc.mesh_of(p)
+        done, t0 = 0, time.perf_counter()
+        while done < ncells:
+            cells = np.arange(done, min(ncells, done + 65536))
+            olift.interpolate_3d(p["level"], m, Q, p["b"], zeta, g=p["params"]["g"], spacing=olift.spacing_of(p),
+                                 cells=cells)
+            done += cells.size
+            if time.perf_counter() - t0 >= args.cpu_seconds:
+                break
+        el = time.perf_counter() - t0
+        out_["cpu_baseline"] = dict(value=done / el, unit="cells/s", cores=1, kind="oracle",
+                                    sample=f"the first {done} cells of the same state ({el:.1f} s, numpy)")
+    print(json.dumps(out_), flush=True)
 
 
 def bench_vam(args, wl, torch, sme, workloads):

@@ -376,6 +376,16 @@ class Solver:
         o = out.cpu().numpy()
         return dict(z=o[0], u=o[1], v=o[2], w=o[3], p=o[4])
 
+    def interpolate_3d_into(self, zeta, out, rho=1.0):
+        """The same lifting into a caller tensor out (torch CUDA float64,
+        contiguous, [5, len(zeta), ncells]), queued on the solver's stream."""
+        z = np.ascontiguousarray(zeta, dtype=np.float64)
+        if not (isinstance(out, torch.Tensor) and out.is_cuda and out.dtype == torch.float64 and out.is_contiguous()
+                and tuple(out.shape) == (5, z.size, self.ncells)):
+            raise TypeError("out must be a contiguous float64 CUDA tensor [5, len(zeta), ncells]")
+        _check(_lib.sme_interpolate_3d(self.ctx, int(z.size), z.ctypes.data_as(ctypes.c_void_p), float(rho),
+                                       ctypes.c_void_p(out.data_ptr())), self.ctx)
+
     def current(self):
         """The bound buffer (torch tensor [nfields, field_stride]) holding the state."""
         return self.q_dev[_lib.sme_current(self.ctx)]
