@@ -43,11 +43,16 @@ def bytes_per_cell(kind, level):
 
 
 def bytes_per_cell_o2(kind, level):
-    """Second-order step on a 1D or structured grid, four launches: two
-    reconstructions (the state and b in, the slopes of the nf + 1
-    reconstruction variables per axis out), stage 1 (state, b and slopes in,
-    Q1 out) and stage 2 (Q1, b, slopes and Q^n in, the new state out)."""
+    """Second-order step.  Structured grids up to level 6, two launches that
+    compute the limited slopes themselves: stage 1 (state and b in, Q1 out),
+    stage 2 (Q1, b and Q^n in, the new state out).  1D grids and higher
+    levels, four launches: two reconstructions (the state and b in, the
+    slopes of the nf + 1 reconstruction variables per axis out), stage 1
+    (state, b and slopes in, Q1 out) and stage 2 (Q1, b, slopes and Q^n in,
+    the new state out)."""
     nf = level + 2 if kind == "1d" else 2 * level + 3
+    if kind == "2d" and level <= 6:
+        return 8 * ((nf + 1) + nf + (nf + 1) + 2 * nf)
     axes = 1 if kind == "1d" else 2
     slopes = axes * (nf + 1)
     recon = (nf + 1) + slopes
@@ -88,11 +93,11 @@ WORKLOADS = {
     "struct_2d_1024_l2_implicit": dict(gen="struct_2d", args=dict(params=dict(implicit_friction=1)),
                                        kernel="k_step_2d",
                                        name="struct_2d_1024x1024_level2_periodic_implicit_friction"),
-    # the default grid with the second-order scheme: a step is four launches
-    "struct_2d_1024_l2_o2": dict(gen="struct_2d", args=dict(params=dict(order=2)), kernel="k_flux2",
+    # the default grid with the second-order scheme: a step is two launches
+    "struct_2d_1024_l2_o2": dict(gen="struct_2d", args=dict(params=dict(order=2)), kernel="k_stage2_band",
                                  name="struct_2d_1024x1024_level2_periodic_second_order",
                                  timing="HIP events on the step stream around the K timed steps, / K (a launch "
-                                        "here is one step: k_recon, k_flux2 stage 1, k_recon, k_flux2 stage 2)"),
+                                        "here is one step: k_stage2_band stage 1 and stage 2)"),
     # 3D lifting of a level-2 1024^2 state to 32 sigma levels
     "lift_1024_l2": dict(gen="lift", args=dict(n=1024, level=2, nz=32), kernel="k_lift",
                          name="lift_3d_1024x1024_level2_32_sigma_levels"),

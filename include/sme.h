@@ -124,7 +124,9 @@ int sme_layout(int level, const sme_mesh *mesh, int *nfields, int64_t *ncells, i
 
 /* Bytes of device memory sme_init allocates for a (level, mesh, params)
  * triple besides the caller's state buffers: bathymetry, Gauss points,
- * time-step slots, the limited slopes of the second-order scheme and, on
+ * time-step slots, the limited slopes of the second-order scheme (1D grids,
+ * and structured grids above level 6: below, the slopes are computed inside
+ * the stages) and, on
  * triangles, neighbours, normals, centroids and the two cell permutations
  * (params NULL: first order).  Attaching a learned closure adds its network
  * and rates buffers. */

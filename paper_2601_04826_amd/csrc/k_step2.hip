@@ -22,8 +22,13 @@
 //   stage 1  Q1 = Q^n + dt L(Q^n)                       (written to the other buffer)
 //   stage 2  Q2 = Q^n / 2 + (Q1 + dt L(Q1)) / 2         (in place over Q^n)
 // then the friction step of the splitting (Eq. (3d)) on Q2, and the CFL ratio
-// of the new state is reduced for the next step (Sec. 3.1).  One lane per
-// cell; blocks are dealt die-major so neighbouring rows share an L2.
+// of the new state is reduced for the next step (Sec. 3.1).
+//
+// Two implementations: on structured grids up to level 6 each stage is one
+// banded launch that computes the slopes itself and evaluates every face once
+// (k_stage2_band, below); on 1D grids and at levels 7-8, k_recon writes the
+// slopes and k_flux2 takes one lane per cell (blocks dealt die-major so
+// neighbouring rows share an L2), each face evaluated by both of its cells.
 #include <hip/hip_runtime.h>
 
 #include "sme_step_common.h"
@@ -281,6 +286,348 @@ __global__ __launch_bounds__(kBlock) void k_flux2(StepArgs a, const double *slop
     }
 }
 
+
+// ---- structured grids: reconstruction fused into the stage, one wave per band
+//
+// A 64-lane wave owns 64 consecutive columns (62 outputs and one halo column
+// on each side) of a band of a.rows rows and marches up the band, as the
+// first-order step does.  Per row it computes the limited slopes itself
+// (along x from the neighbouring lanes, the two edge lanes reading their
+// outer neighbour; along y from the rows below and above, held in registers),
+// the four reconstructed face values of each cell with their fluxes, the
+// x-face to the right of each lane (the right cell's share moves one lane up),
+// the y-face between the previous and the current row (the previous row's
+// upper face value held in registers) and both in-cell fluctuations.  Each
+// face is evaluated once; no slopes array is written or read.  The slopes,
+// face values and faces are computed by the same code from the same inputs
+// whichever wave computes them, so results do not depend on the cut into
+// strips and bands.
+
+// index of column or row c of a grid of n with up to two halo cells per side:
+// periodic ends wrap; beyond a wall or open end the nearest cell (mirror:
+// the ghost of a wall, whose normal momenta change sign)
+__device__ __forceinline__ int halo_index(int c, int n, int bc_lo, int bc_hi, bool &mirror)
+{
+    mirror = false;
+    if (c < 0) {
+        if (bc_lo == BC_PERIODIC) return ((c % n) + n) % n;
+        mirror = bc_lo == BC_WALL;
+        return 0;
+    }
+    if (c >= n) {
+        if (bc_hi == BC_PERIODIC) return c % n;
+        mirror = bc_hi == BC_WALL;
+        return n - 1;
+    }
+    return c;
+}
+
+// the reconstruction variables (eta = h + b, qx, qy, b) of the cell at
+// (column col, row row), x momenta mirrored if mx, y momenta if my
+template <int N>
+__device__ __forceinline__ void load_rv(const StepArgs &a, int col, int row, bool mx, bool my, double *v)
+{
+    constexpr int n = N + 1, nf = 2 * n + 1;
+    const int64_t c = (int64_t)row * a.nx + col;
+    const double h = a.q[c], b = a.b[c];
+    v[0] = h + b;
+#pragma unroll
+    for (int k = 0; k < n; ++k) {
+        const double qx = a.q[(int64_t)(1 + k) * a.stride + c];
+        const double qy = a.q[(int64_t)(1 + n + k) * a.stride + c];
+        v[1 + k] = mx ? -qx : qx;
+        v[1 + n + k] = my ? -qy : qy;
+    }
+    v[nf] = b;
+}
+
+// one row of the wave: this lane's column, mapped, and its mirror flags
+struct Lane2 {
+    int col;      // column of this lane (halo columns mapped)
+    bool mx;      // this lane's column is a wall ghost
+    int colo;     // outer neighbour column of an edge lane (lane 0: c - 1, lane 63: c + 1)
+    bool mxo;
+};
+
+// reconstruction variables of row j at this lane, and the outer neighbour's
+// for the two edge lanes
+template <int N>
+__device__ __forceinline__ void load_row_rv(const StepArgs &a, const Lane2 &L, int j, double *v, double *vo,
+                                            bool edge)
+{
+    bool my;
+    const int row = halo_index(j, a.ny, a.bc[2], a.bc[3], my);
+    load_rv<N>(a, L.col, row, L.mx, my, v);
+    if (edge) load_rv<N>(a, L.colo, row, L.mxo, my, vo);
+}
+
+// Face value of a cell on side hs of axis AX (normal +axis frame) from its
+// variables v and slopes s, with the flux of that side.
+template <int N, int AX>
+__device__ __forceinline__ void rv_side(const double *v, const double *s, double hs, double g, Side<N, true> &S)
+{
+    constexpr int n = N + 1, nf = 2 * n + 1;
+    const double b = v[nf] + hs * s[nf];
+    const double eta = v[0] + hs * s[0];
+    S.h = eta - b;
+    S.b = b;
+#pragma unroll
+    for (int k = 0; k < n; ++k) {
+        const double qx = v[1 + k] + hs * s[1 + k];
+        const double qy = v[1 + n + k] + hs * s[1 + n + k];
+        S.qa[k] = AX == 0 ? qx : qy;
+        S.qt[k] = AX == 0 ? qy : -qx;
+    }
+    side_flux<N, true>(S, g);
+}
+
+// the value outside a wall or open end: this side's value, the normal
+// momenta (and so the tangential flux block) negated at a wall
+template <int N>
+__device__ __forceinline__ void outside_of(const Side<N, true> &s, bool wall, Side<N, true> &o)
+{
+    o = s;
+    if (wall) {
+#pragma unroll
+        for (int k = 0; k <= N; ++k) {
+            o.qa[k] = -s.qa[k];
+            o.Ft[k] = -s.Ft[k];
+        }
+    }
+}
+
+template <int N>
+__device__ __forceinline__ void shfl_dn_side(const Side<N, true> &s, Side<N, true> &r)
+{
+    r.h = shfl_dn(s.h);
+    r.b = shfl_dn(s.b);
+    r.lam = shfl_dn(s.lam);
+#pragma unroll
+    for (int k = 0; k <= N; ++k) {
+        r.qa[k] = shfl_dn(s.qa[k]);
+        r.qt[k] = shfl_dn(s.qt[k]);
+        r.Fa[k] = shfl_dn(s.Fa[k]);
+        r.Ft[k] = shfl_dn(s.Ft[k]);
+    }
+}
+
+// in-cell fluctuation of axis AX from the minus to the plus face value, added
+// to the physical-order accumulator with weight w
+template <int N, int AX>
+__device__ __forceinline__ void in_cell(const StepArgs &a, const Side<N, true> &m, const Side<N, true> &p, double w,
+                                        double *acc)
+{
+    constexpr int n = N + 1, nf = 2 * n + 1;
+    double dqa[n], dqt[n], D[nf];
+#pragma unroll
+    for (int k = 0; k < n; ++k) {
+        dqa[k] = p.qa[k] - m.qa[k];
+        dqt[k] = p.qt[k] - m.qt[k];
+    }
+    nc_fluct<N, true>(m, p, a.g, a.quad, dqa, dqt, D);
+    add_frame<N, 2>(acc, D, AX, w);
+}
+
+// the stage update of a finished cell (row j, this lane), and for stage 2
+// friction, the non-physical-state flag and the CFL ratio of the result
+template <int N, int STAGE, bool IMP>
+__device__ __forceinline__ double finish2(const StepArgs &a, double dt, int j, int c, bool out, const double *acc,
+                                          long long step1)
+{
+    constexpr int n = N + 1, nf = 2 * n + 1;
+    if (!out) return 0.0;
+    const int64_t i = (int64_t)j * a.nx + c;
+    double qnew[nf];
+#pragma unroll
+    for (int f = 0; f < nf; ++f) {
+        const double q1 = fma(-dt, acc[f], a.q[(int64_t)f * a.stride + i]);
+        qnew[f] = STAGE == 1 ? q1 : 0.5 * a.qn[(int64_t)f * a.stride + i] + 0.5 * q1;
+    }
+    double r = 0.0;
+    if constexpr (STAGE == 2) {
+        const double ih = rcp(qnew[0]);
+        friction_step<N, true, IMP>(qnew + 1, qnew + 1 + n, ih, dt, a.c_slip, a.nu);
+        bool bad = !(qnew[0] > 0.0) || !isfinite(qnew[0]);
+#pragma unroll
+        for (int f = 1; f < nf; ++f) bad |= !isfinite(qnew[f]);
+        flag_bad_at(a, bad, step1);
+        double lm;
+        r = cfl_ratio_2d<N>(a.g, qnew[0], ih, qnew + 1, qnew + 1 + n, a.idx, a.idy, &lm);
+        if (!(r >= 0.0)) r = 0.0;
+    }
+#pragma unroll
+    for (int f = 0; f < nf; ++f) a.qn[(int64_t)f * a.stride + i] = qnew[f];
+    return r;
+}
+
+// limited slope of variable f along x of this lane's cell, from its
+// neighbours' values (lanes -/+ 1, or the edge lanes' outer neighbours vo)
+__device__ __forceinline__ double slope_x(const double *v, const double *vo, int lane, int f)
+{
+    const double vl = shfl_up1(v[f]), vr = shfl_dn(v[f]);
+    const double l = lane == 0 ? vo[f] : vl;
+    const double r = lane == kWave - 1 ? vo[f] : vr;
+    return minmod(v[f] - l, r - v[f]);
+}
+
+// Whole band (strip sxi, band syi) of one stage; returns the largest CFL
+// ratio of the cells written (stage 2).  All 64 lanes of the wave must call
+// it.  Per row the work is ordered so that one slope vector and at most three
+// face values are live at a time.
+template <int N, int STAGE, bool IMP>
+__device__ __forceinline__ double band2_o2(const StepArgs &a, double dt, int sxi, int syi, long long step1)
+{
+    constexpr int n = N + 1, nf = 2 * n + 1, nv = nf + 1;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int c = sxi * kOut - 1 + lane;
+    const int j0 = syi * a.rows;
+    const int j1 = min(j0 + a.rows, a.ny);
+    Lane2 L;
+    L.col = halo_index(c, a.nx, a.bc[0], a.bc[1], L.mx);
+    L.colo = halo_index(lane == 0 ? c - 1 : c + 1, a.nx, a.bc[0], a.bc[1], L.mxo);
+    const bool edge = lane == 0 || lane == kWave - 1;
+    const bool outc = lane >= 1 && lane <= kOut && c < a.nx;
+    // x boundary faces: this lane's face to the right is the west boundary
+    // (c == -1) or the east boundary (c == nx - 1); the inner cell's own face
+    // value stands outside
+    const bool bnd_lo = c == -1 && a.bc[0] != BC_PERIODIC;
+    const bool bnd_hi = c == a.nx - 1 && a.bc[1] != BC_PERIODIC;
+    const bool wall_lo = a.bc[0] == BC_WALL, wall_hi = a.bc[1] == BC_WALL;
+    double vd[nv], v[nv], vu[nv], vo[nv];
+    double rmax = 0.0;
+    // rows j0 - 2 .. j0 - 1 in registers: the slopes of the halo row j0 - 1 need the row below it
+    load_row_rv<N>(a, L, j0 - 2, vd, vo, false);
+    load_row_rv<N>(a, L, j0 - 1, v, vo, edge);
+    Side<N, true> Pp;  // upper face value of the previous row
+    double accP[nf];   // the previous row's accumulator
+    for (int j = j0 - 1; j <= j1; ++j) {
+        // v: row j (vo: its edge-lane outer neighbours); vd: row j - 1
+        load_row_rv<N>(a, L, j + 1, vu, vo, false);
+        // first order where a face depth would not be positive (eta and b slopes of both axes)
+        bool ok = true;
+        {
+            const double se = slope_x(v, vo, lane, 0), sb = slope_x(v, vo, lane, nf);
+            const double te = minmod(v[0] - vd[0], vu[0] - v[0]), tb = minmod(v[nf] - vd[nf], vu[nf] - v[nf]);
+#pragma unroll
+            for (int side = 0; side < 2; ++side) {
+                const double hs = side ? 0.5 : -0.5;
+                ok = ok && ((v[0] + hs * se) - (v[nf] + hs * sb) > 0.0);
+            }
+#pragma unroll
+            for (int side = 0; side < 2; ++side) {
+                const double hs = side ? 0.5 : -0.5;
+                ok = ok && ((v[0] + hs * te) - (v[nf] + hs * tb) > 0.0);
+            }
+        }
+        double sl[nv];
+#pragma unroll
+        for (int f = 0; f < nv; ++f) sl[f] = ok ? minmod(v[f] - vd[f], vu[f] - v[f]) : 0.0;
+        Side<N, true> ym;
+        rv_side<N, 1>(v, sl, -0.5, a.g, ym);
+        double accC[nf];
+        if (j >= j0) {
+            // y-face between rows j - 1 (Pp) and j (ym); at a south or north
+            // wall or open end the inner value stands outside
+            if (j == 0 && a.bc[2] != BC_PERIODIC) outside_of<N>(ym, a.bc[2] == BC_WALL, Pp);
+            if (j == a.ny && a.bc[3] != BC_PERIODIC) outside_of<N>(Pp, a.bc[3] == BC_WALL, ym);
+            double Fh[nf], D[nf];
+            face_flux<N, true>(Pp, ym, a.g, a.quad, Fh, D);
+            if (j > j0) {
+                double C[nf];
+#pragma unroll
+                for (int f = 0; f < nf; ++f) C[f] = fma(0.5, D[f], Fh[f]);
+                add_frame<N, 2>(accP, C, 1, a.idy);
+                rmax = fmax(rmax, finish2<N, STAGE, IMP>(a, dt, j - 1, c, outc, accP, step1));
+            }
+            if (j == j1) break;
+#pragma unroll
+            for (int f = 0; f < nf; ++f) accC[f] = 0.0;
+            double C[nf];
+#pragma unroll
+            for (int f = 0; f < nf; ++f) C[f] = fma(0.5, D[f], -Fh[f]);
+            add_frame<N, 2>(accC, C, 1, a.idy);
+        }
+        rv_side<N, 1>(v, sl, 0.5, a.g, Pp);
+        if (j >= j0) {
+            in_cell<N, 1>(a, ym, Pp, a.idy, accC);
+#pragma unroll
+            for (int f = 0; f < nv; ++f) sl[f] = ok ? slope_x(v, vo, lane, f) : 0.0;
+            Side<N, true> xm, xp;
+            rv_side<N, 0>(v, sl, -0.5, a.g, xm);
+            rv_side<N, 0>(v, sl, 0.5, a.g, xp);
+            in_cell<N, 0>(a, xm, xp, a.idx, accC);
+            // x-face to the right: this lane's plus value, the next lane's minus value
+            Side<N, true> R;
+            shfl_dn_side<N>(xm, R);
+            if (bnd_lo) outside_of<N>(R, wall_lo, xp);
+            if (bnd_hi) outside_of<N>(xp, wall_hi, R);
+            double Gh[nf], E[nf];
+            face_flux<N, true>(xp, R, a.g, a.quad, Gh, E);
+#pragma unroll
+            for (int f = 0; f < nf; ++f) {
+                const double own = fma(0.5, E[f], Gh[f]);
+                const double oth = fma(0.5, E[f], -Gh[f]);
+                accP[f] = fma(a.idx, own + shfl_up1(oth), accC[f]);
+            }
+        }
+#pragma unroll
+        for (int f = 0; f < nv; ++f) {
+            vd[f] = v[f];
+            v[f] = vu[f];
+        }
+        // the edge lanes' outer neighbours of the next row
+        if (edge) {
+            bool my;
+            const int row = halo_index(j + 1, a.ny, a.bc[2], a.bc[3], my);
+            load_rv<N>(a, L.colo, row, L.mxo, my, vo);
+        }
+    }
+    return rmax;
+}
+
+// resident waves per SIMD the band stages aim for: two while the row's live
+// set fits 256 registers, one above (the accumulation registers then hold
+// what does not fit)
+template <int N>
+constexpr int waves_o2()
+{
+    return N <= 1 ? 2 : 1;
+}
+
+// STAGE 1: Q1 = Q^n + dt L(Q^n) into a.qn.  STAGE 2: Q = Q^n / 2 + (Q1 + dt L(Q1)) / 2
+// in place over a.qn (= Q^n), then friction, the CFL ratio of the result.
+template <int N, int STAGE, bool IMP>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(waves_o2<N>()))) void k_stage2_band(StepArgs a)
+{
+    constexpr int nf = 2 * N + 3;
+    const double dt = step_dt(a);
+    if (STAGE == 2 && blockIdx.x == 0 && threadIdx.x == 0) slot_update(a, dt);
+    if (dt == 0.0) {
+        // past the end time: the state stays and the CFL ratio carries over
+        const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+        const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+        if (STAGE == 1)
+            for (int f = 0; f < nf; ++f)
+                for (int64_t i = t0; i < a.ncells; i += nth) a.qn[f * a.stride + i] = a.q[f * a.stride + i];
+        if (STAGE == 2 && t0 == 0) {
+#pragma unroll
+            for (int w = 0; w < kRatioWords; ++w) a.slots[a.sb].r[w].bits = a.slots[a.sa].r[w].bits;
+            a.slots[a.sb].lbits = a.slots[a.sa].lbits;
+        }
+        return;
+    }
+    const int nsx = (a.nx + kOut - 1) / kOut;
+    const int nsy = (a.ny + a.rows - 1) / a.rows;
+    const int nblk = (int)gridDim.x;
+    const int per_xcd = (nblk + kXcd - 1) / kXcd;
+    const int slot = (int)(blockIdx.x % kXcd) * per_xcd + (int)(blockIdx.x / kXcd);
+    const int wave = __builtin_amdgcn_readfirstlane(slot * (kBlock / kWave) + (int)(threadIdx.x >> 6));
+    const long long st = a.slots[a.sa].step + 1;
+    double rmax = 0.0;
+    if (wave < nsx * nsy) rmax = band2_o2<N, STAGE, IMP>(a, dt, wave % nsx, wave / nsx, st);
+    if constexpr (STAGE == 2) publish_ratio(a.slots[a.sb], rmax);
+}
+
 }  // namespace
 
 unsigned step2_grid(int64_t ncells) { return (blocks_for(ncells) + kXcd - 1) / kXcd * kXcd; }
@@ -297,6 +644,43 @@ hipError_t launch_recon2(int level, int dim, const StepArgs &a, double *slopes, 
     }
 #undef RC1
 #undef RC2
+    return hipGetLastError();
+}
+
+hipError_t launch_stage2_band(int level, int stage, const StepArgs &a, hipStream_t s)
+{
+    const int64_t nsx = (a.nx + kOut - 1) / kOut;
+    const int64_t nsy = (a.ny + a.rows - 1) / a.rows;
+    const int64_t blocks = (nsx * nsy * kWave + kBlock - 1) / kBlock;
+    const unsigned grid = (unsigned)((blocks + kXcd - 1) / kXcd * kXcd);
+#define B(N, S, I) hipLaunchKernelGGL((k_stage2_band<N, S, I>), dim3(grid), dim3(kBlock), 0, s, a)
+#define B1(N) B(N, 1, false)
+#define B2(N) B(N, 2, false)
+#define B2I(N) B(N, 2, true)
+#define BAND_SWITCH(CALL)        \
+    switch (level) {             \
+    case 0: CALL(0); break;      \
+    case 1: CALL(1); break;      \
+    case 2: CALL(2); break;      \
+    case 3: CALL(3); break;      \
+    case 4: CALL(4); break;      \
+    case 5: CALL(5); break;      \
+    case 6: CALL(6); break;      \
+    default: return hipErrorInvalidValue; \
+    }
+    static_assert(kStage2BandMaxLevel == 6, "the switch below lists the band levels");
+    if (stage == 1) {
+        BAND_SWITCH(B1)
+    } else if (a.implicit) {
+        BAND_SWITCH(B2I)
+    } else {
+        BAND_SWITCH(B2)
+    }
+#undef BAND_SWITCH
+#undef B
+#undef B1
+#undef B2
+#undef B2I
     return hipGetLastError();
 }
 

@@ -132,6 +132,12 @@ hipError_t launch_step_tri(int level, const StepArgs &a, hipStream_t s);
 // (a.q + dt L(a.q)) / 2, friction, CFL ratio) of the two-stage Runge-Kutta step
 hipError_t launch_recon2(int level, int dim, const StepArgs &a, double *slopes, hipStream_t s);
 hipError_t launch_flux2(int level, int dim, int stage, const StepArgs &a, const double *slopes, hipStream_t s);
+// the same stages on structured grids with the reconstruction fused in (no
+// slopes array): one wave per band of a.rows rows, as launch_step_2d; levels
+// 0 .. kStage2BandMaxLevel (above, the row's live set no longer fits the
+// registers of one wave)
+constexpr int kStage2BandMaxLevel = 6;
+hipError_t launch_stage2_band(int level, int stage, const StepArgs &a, hipStream_t s);
 hipError_t launch_eig(int dim, int kind, int level, const StepArgs &a, hipStream_t s);
 hipError_t launch_slots_reset(Slot *slots, ErrWord *err, int sa, hipStream_t s);  // err may be null
 // closure network training and samples (k_mlp.hip)

@@ -79,7 +79,9 @@ struct sme_ctx {
     float *rates = nullptr;             // closure rates of the current state (2 or 4 per cell)
     int closure_mode = 0;               // ClosurePrecision of the attached network
     double *ckpt = nullptr;             // state at the start of a closure chunk (sme_closure_run)
-    double *slopes = nullptr;           // limited slopes of the second-order scheme
+    bool order2 = false;                // the second-order scheme
+    double *slopes = nullptr;           // its limited slopes (1D grids, and structured grids above
+                                        // the levels of the fused band stages)
     double *t_host = nullptr;           // pinned: simulated time after the latest graph with an end time
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};  // completion of the last graphs of a run
     int cus = 256;                      // compute units of the device
@@ -187,22 +189,32 @@ StepArgs make_args(const sme_ctx *c)
     return a;
 }
 
+// the second-order scheme keeps a slopes array on 1D grids and on structured
+// grids above the levels of the fused band stages
+bool needs_slopes(int kind, int level) { return kind != SME_MESH_2D_STRUCT || level > kStage2BandMaxLevel; }
+
 hipError_t launch_one_step(sme_ctx *c, double dt_fixed, double t_end)
 {
     StepArgs a = make_args(c);
     a.dt_fixed = dt_fixed;
     a.t_end = t_end;
     hipError_t e = hipSuccess;
-    if (c->slopes) {
+    if (c->order2) {
         // second order: stage 1 into the other buffer, stage 2 back in place
         const int dim = c->kind == SME_MESH_1D ? 1 : 2;
-        e = launch_recon2(c->level, dim, a, c->slopes, c->stream);
-        if (e == hipSuccess) e = launch_flux2(c->level, dim, 1, a, c->slopes, c->stream);
         StepArgs a2 = a;
         a2.q = a.qn;
         a2.qn = const_cast<double *>(a.q);
-        if (e == hipSuccess) e = launch_recon2(c->level, dim, a2, c->slopes, c->stream);
-        if (e == hipSuccess) e = launch_flux2(c->level, dim, 2, a2, c->slopes, c->stream);
+        if (!c->slopes) {
+            // structured grid: the reconstruction fused into the band stages
+            e = launch_stage2_band(c->level, 1, a, c->stream);
+            if (e == hipSuccess) e = launch_stage2_band(c->level, 2, a2, c->stream);
+        } else {
+            e = launch_recon2(c->level, dim, a, c->slopes, c->stream);
+            if (e == hipSuccess) e = launch_flux2(c->level, dim, 1, a, c->slopes, c->stream);
+            if (e == hipSuccess) e = launch_recon2(c->level, dim, a2, c->slopes, c->stream);
+            if (e == hipSuccess) e = launch_flux2(c->level, dim, 2, a2, c->slopes, c->stream);
+        }
         if (e == hipSuccess) c->sa = (c->sa + 1) % 3;
         return e;
     }
@@ -314,7 +326,7 @@ int sme_workspace_size(int level, const sme_mesh *mesh, const sme_params *params
     const size_t st = (size_t)stride_of(nc);
     size_t n = st * sizeof(double)                 // bathymetry (internal order)
                + 3 * sizeof(Slot) + sizeof(ErrWord) + 2 * kMaxQuad * sizeof(double);
-    if (params && params->order == 2)  // limited slopes of the second-order scheme
+    if (params && params->order == 2 && needs_slopes(mesh->kind, level))  // limited slopes of the second-order scheme
         n += (size_t)(mesh->kind == SME_MESH_1D ? 1 : 2) * (nf + 1) * st * sizeof(double);
     if (mesh->kind == SME_MESH_2D_TRI)
         n += 3 * st * (sizeof(int32_t) + 3 * sizeof(double))  // neighbours, normals, |e|/|V|
@@ -393,7 +405,8 @@ int sme_init(sme_ctx **out, int level, const sme_mesh *mesh, const sme_params *p
         rc = check_device_buffer(c, q_dev[k], (size_t)nf * c->stride * sizeof(double));
     }
     rc = rc ? rc : dalloc(c, &c->b, (size_t)c->stride);
-    if (params->order == 2)
+    c->order2 = params->order == 2;
+    if (c->order2 && needs_slopes(mesh->kind, level))
         rc = rc ? rc : dalloc(c, &c->slopes, (size_t)(mesh->kind == SME_MESH_1D ? 1 : 2) * (nf + 1) * c->stride);
     rc = rc ? rc : dalloc(c, &c->slots, 3);
     rc = rc ? rc : dalloc(c, &c->err, 1);
@@ -579,7 +592,7 @@ int sme_run(sme_ctx *c, int64_t n_steps, double t_end, double *t_out, int64_t *s
     // a small 1D grid without a closure: one workgroup takes the steps with the
     // state in LDS, up to kLdsRunSteps per launch (checking the clock between
     // launches when there is an end time)
-    if (c->kind == SME_MESH_1D && !c->closure && !c->slopes && getenv("SME_NO_LDS_RUN") == nullptr &&
+    if (c->kind == SME_MESH_1D && !c->closure && !c->order2 && getenv("SME_NO_LDS_RUN") == nullptr &&
         (c->nx + 61) / 62 <= kLdsRunMaxWindows[c->level] &&
         run_1d_lds_bytes(c->level, (int)c->nx) + 1024 <= c->lds_optin) {
         while (left > 0) {
@@ -725,7 +738,7 @@ __attribute__((visibility("hidden"))) int sme_internal_attach(sme_ctx *c, const 
         drop_graphs(c);
         return SME_OK;
     }
-    if (c->level != 1 || c->kind == SME_MESH_2D_TRI || c->slopes)
+    if (c->level != 1 || c->kind == SME_MESH_2D_TRI || c->order2)
         return fail(c, SME_EINVAL, "the learned closure acts on level-1 1D and structured 2D grids, first order");
     if (!c->closure) {
         if (dalloc(c, &c->closure, 1)) return SME_ENOMEM;

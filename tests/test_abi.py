@@ -90,9 +90,17 @@ def test_workspace_size(sme):
     t, _ = sme.make_mesh(dict(kind="tri", vert=vert, tri=np.array([[0, 1, 2], [1, 3, 2]], dtype=np.int32)))
     wt = sme.sme_workspace_size(3, t)
     assert wt >= 256 * 8 + 3 * 256 * (4 + 24) + 2 * 2 * 8
-    # the second-order scheme adds the slopes of 2 axes x (nfields + 1) variables
+    # the second-order scheme on a structured grid computes its slopes inside
+    # the stages up to level 6; above, it keeps 2 axes x (nfields + 1) of them
     w2 = sme.sme_workspace_size(2, m, sme.make_params(order=2))
-    assert w2 - ws == 2 * 8 * st * 8
+    assert w2 == ws
+    nf7, _, st7 = sme.sme_layout(7, m)
+    w7 = sme.sme_workspace_size(7, m, sme.make_params(order=2)) - sme.sme_workspace_size(7, m)
+    assert w7 == 2 * (nf7 + 1) * st7 * 8
+    m1, _ = sme.make_mesh(dict(kind="1d", nx=1000, x0=0, x1=1, bc=("wall", "wall")))
+    nf1, _, st1 = sme.sme_layout(3, m1)
+    w1 = sme.sme_workspace_size(3, m1, sme.make_params(order=2)) - sme.sme_workspace_size(3, m1)
+    assert w1 == (nf1 + 1) * st1 * 8
 
 
 def test_strerror(sme):
