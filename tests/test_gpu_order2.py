@@ -77,13 +77,26 @@ def test_order2_levels_1d(sme, level):
         assert abs(t_gpu - t_orc) <= 1e-12 * t_orc
 
 
-@pytest.mark.parametrize("level", [0, 1, 2, 3, 4, 8])
+@pytest.mark.parametrize("level", range(0, 9))
 def test_order2_levels_2d(sme, level):
+    """Every level: 0-6 run the banded stages, 7-8 the reconstruction +
+    per-cell stages."""
     for bc in (("wall", "wall", "periodic", "periodic"), ("periodic", "periodic", "extrap", "wall")):
         p = with_moments(W.struct_2d(n=45, level=level, L=4.5, bc=bc), 20 + level)
         q_gpu, q_orc, t_gpu, t_orc = run_both(sme, p, 40, **O2)
         assert rel_linf(q_gpu, q_orc) <= 1e-10, bc
         assert abs(t_gpu - t_orc) <= 1e-12 * t_orc
+
+
+@pytest.mark.parametrize("level", [3, 6])
+def test_order2_strips_and_bands(sme, level):
+    """Three strips of columns and several bands of rows at the levels that
+    run one wave per SIMD, with a wall, an open end and periodic ends."""
+    p = with_moments(W.struct_2d(n=130, level=level, L=13.0, bc=("wall", "extrap", "periodic", "periodic")),
+                     40 + level)
+    q_gpu, q_orc, t_gpu, t_orc = run_both(sme, p, 20, **O2)
+    assert rel_linf(q_gpu, q_orc) <= 1e-10
+    assert abs(t_gpu - t_orc) <= 1e-12 * t_orc
 
 
 def test_order2_struct_128_1000_steps(sme):
