@@ -53,8 +53,14 @@ def oracle_of(p):
     return vam.Vam1D(p["nx"], p["x0"], p["x1"], b=p["b"], g=prm["g"], cfl=prm["cfl"], quad_points=prm["quad_points"])
 
 
-@pytest.mark.parametrize("n", [1, 2, 3, 5, 8, 63, 64, 257, 1000, 2001])
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 8, 63, 64, 127, 128, 129, 130, 257, 1000, 1021, 1022, 1024, 1025, 2001])
 def test_one_step_matches_oracle(sme, n):
+    """Sizes around the solver's boundaries: a system of up to 64 blocks is
+    solved entirely in LDS by one wave (n <= 128 cells), a larger one first
+    reduces level by level; a reduction workgroup takes 256 even and 255 odd
+    blocks, so 511, 512 and 513 blocks (n = 1021 .. 1025) put the last odd
+    block at the end of a workgroup, alone in a second one, or leave a
+    second workgroup with only its even block."""
     print(f"case vam one step n={n}", flush=True)
     p = W.vam_1d(n=n, L=20.0)
     v = sme.Vam(p)
