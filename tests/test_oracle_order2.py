@@ -9,7 +9,11 @@ path fluctuation, two-stage SSP Runge-Kutta), on 1D and structured grids.
   operator is the first-order one exactly (same faces, no in-cell term);
 * the lake at rest stays at rest to round-off over any bed (free-surface
   reconstruction); mass is conserved on periodic domains;
-* the wet dam break (Stoker) is approximated better than at first order;
+* the wet dam break (Stoker) is approximated better than at first order, and
+  its depths stay within the initial range (the limiter takes the smaller
+  one-sided difference);
+* a cell whose reconstruction would give a negative face depth falls back to
+  zero slopes;
 * 1D equals 2D with one row; the 2D step is invariant under a 90 deg rotation.
 """
 import math
@@ -99,6 +103,35 @@ def test_lake_at_rest_order2(N):
     Q2, _ = o2.run(Q, 100)
     assert np.max(np.abs(Q2[1:])) <= 1e-12
     assert np.max(np.abs(Q2[0] - Q[0])) <= 1e-12
+
+
+def test_dam_break_stays_within_initial_depths_order2():
+    """The minmod limiter takes the smaller one-sided difference, so no
+    reconstructed face value leaves the range of the neighbouring averages:
+    the wet dam break (2 m against 1 m) keeps every depth inside [1, 2] (a
+    limiter that took the larger difference overshoots by several per cent)."""
+    for level in (0, 1):
+        p = W.dam_break_1d(n=400, level=level, hl=2.0, hr=1.0)
+        o = sme.from_problem(p, order=2, c_slip=0.0, nu=0.0)
+        Q, _ = o.run(p["q"], 300)
+        assert Q[0].max() <= 2.0 + 1e-12 and Q[0].min() >= 1.0 - 1e-12
+
+
+def test_negative_face_depth_falls_back_to_first_order():
+    """A shallow cell at the foot of a bed step: its free surface is a local
+    minimum (zero slope) while the bed rises, so the linear reconstruction
+    would put a negative depth (0.05 - 0.3 / 2) on its upper face.  The cell
+    keeps zero slopes instead, and the step stays finite with positive
+    depths."""
+    n = 8
+    m = mesh.mesh_1d(n, 0.0, 0.8, ("wall", "wall"))
+    b = np.array([0.0, 0.0, 0.0, 0.3, 0.6, 0.6, 0.6, 0.6])
+    Q = np.zeros((2, n))
+    Q[0] = [0.5, 0.5, 0.5, 0.05, 0.5, 0.5, 0.5, 0.5]
+    o = sme.Oracle(0, m, b, order=2)
+    Q1, _ = o.step(Q, 1e-3)
+    assert np.all(np.isfinite(Q1))
+    assert Q1[0].min() > 0.0
 
 
 def test_mass_conservation_order2():
