@@ -54,6 +54,25 @@ def test_adam_closed_form_first_step():
     np.testing.assert_allclose(v1, 0.001 * g * g, rtol=1e-14)
 
 
+def test_adam_constant_gradient_moves_lr_per_step():
+    """With a constant gradient the bias-corrected moments are exactly g and
+    g^2 at every step t (m_t = (1 - b1^t) g, v_t = (1 - b2^t) g^2), so each
+    step moves every parameter by lr g / (|g| + eps): pins the corrections'
+    powers of t beyond the first step."""
+    rng = np.random.default_rng(4)
+    p = rng.standard_normal(40)
+    g = rng.standard_normal(40)
+    m = np.zeros(40)
+    v = np.zeros(40)
+    lr = 2e-3
+    for t in range(1, 6):
+        p_next, m, v = mlp.adam(p, g, m, v, t, lr)
+        np.testing.assert_allclose(p - p_next, lr * g / (np.abs(g) + 1e-8), rtol=1e-9)
+        np.testing.assert_allclose(m, (1.0 - 0.9 ** t) * g, rtol=1e-12)
+        np.testing.assert_allclose(v, (1.0 - 0.999 ** t) * g * g, rtol=1e-12)
+        p = p_next
+
+
 def test_zero_network_outputs_zero():
     y, _ = mlp.forward(np.zeros(mlp.NPARAM), np.random.default_rng(0).standard_normal((7, mlp.NIN)))
     assert np.all(y == 0.0)
@@ -66,3 +85,18 @@ def test_features_periodic_differences():
     f = mlp.features_1d(h, q0, q1)
     np.testing.assert_array_equal(f[0], [1, 0, 3, 1, 1, 0, -3, 0, -2])
     np.testing.assert_array_equal(f[2], [4, 0, 5, -3, 0, -2, 2, -1, 2])
+
+
+def test_closure_target_turns_level1_step_into_level8():
+    """The target is the rate of q_0, q_1 that, added over one step to the
+    level-1 step from the level-8 state, gives the level-8 result: level-1
+    step + dt * target = level-8 next state (up to rounding), whatever the
+    level-8 state before the step."""
+    rng = np.random.default_rng(5)
+    n, dt = 33, 1e-3
+    q8_now = rng.uniform(0.5, 1.5, (10, n))
+    q8_next = q8_now + rng.uniform(-0.01, 0.01, (10, n))
+    q1_step = q8_now[:4] + rng.uniform(-0.01, 0.01, (4, n))
+    t = mlp.closure_target(q8_now, q8_next, q1_step, dt)
+    assert t.shape == (n, 2)
+    np.testing.assert_allclose(q1_step[1:3] + dt * t.T, q8_next[1:3], rtol=0, atol=1e-14)
