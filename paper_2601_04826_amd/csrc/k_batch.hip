@@ -2,8 +2,10 @@
 // one persistent launch per step.
 //
 // The work list holds one item per (grid, strip, band), sorted by level
-// (costliest first) so that the static round-robin deal over the resident
-// waves gives every wave a similar mix.  Each grid keeps its own three time
+// (costliest first).  Each resident wave takes the next item from a device
+// counter when it is done with the previous one, so the waves finish together
+// even when the items are few and tall (a fixed deal of a few tall items per
+// wave leaves some waves one item behind the rest).  Each grid keeps its own three time
 // slots, so every grid takes its own CFL step; the item holding the grid's
 // first band also advances that grid's clock.  The band code is the one of the
 // single-grid kernel, so a grid advanced here is bitwise identical to the same
@@ -23,13 +25,21 @@ template <bool IMP>
 __global__ __launch_bounds__(kBlock) void k_batch_step(BatchArgs B)
 {
     const int lane = threadIdx.x & (kWave - 1);
-    const int nwaves = (int)gridDim.x * (kBlock / kWave);
-    const int w = __builtin_amdgcn_readfirstlane((int)blockIdx.x * (kBlock / kWave) + (int)(threadIdx.x >> 6));
     // one staging area per wave, sized for the highest level of the ensemble
     constexpr int sd = stage_doubles<kBatchMaxLevel>();
     __shared__ __attribute__((aligned(16))) double stage_all[(kBlock / kWave) * sd];
     double *const stage = stage_all + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) * sd;
-    for (int it = w; it < B.nitems; it += nwaves) {
+    // This step counts on work[sa] and clears work[sc] for the step after
+    // next (the next step counts on work[sb], which the previous step cleared).
+    unsigned *const ctr = B.work + B.sa * kWorkStride;
+    if (blockIdx.x == 0 && threadIdx.x == 0) (void)atomicExch(B.work + B.sc * kWorkStride, 0u);
+    unsigned got = 0;
+    if (lane == 0) got = atomicAdd(ctr, 1u);
+    int it = (int)__builtin_amdgcn_readfirstlane(got);
+    while (it < B.nitems) {
+        // the index of the wave's next item is fetched while this one runs
+        got = 0;
+        if (lane == 0) got = atomicAdd(ctr, 1u);
         const BatchItem item = B.items[it];
         const BatchInst I = B.inst[item.inst];
         StepArgs a;
@@ -79,6 +89,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_step(BatchArgs B)
         r = wave_max(r);
         if (lane == 0 && r > 0.0)
             atomicMax(&a.slots[a.sb].r[blockIdx.x % kRatioWords].bits, (unsigned long long)__double_as_longlong(r));
+        it = (int)__builtin_amdgcn_readfirstlane(got);
     }
 }
 

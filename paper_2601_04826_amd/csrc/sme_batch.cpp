@@ -1,9 +1,9 @@
 // sme_batch.cpp -- host side of the batched ensemble (sme_batch_* in include/sme.h).
 //
 // All grids live in two packed state arenas (ping-pong) and one bathymetry
-// arena.  The work list holds one item per (grid, strip, band); one
-// persistent launch per step deals the items round-robin to the resident
-// waves.  Runs of six steps are captured as HIP graphs (six = lcm of the
+// arena.  The work list holds one item per (grid, strip, band); in one
+// persistent launch per step the resident waves take the items in list order
+// from a device counter.  Runs of six steps are captured as HIP graphs (six = lcm of the
 // arena ping-pong period 2 and the time-slot period 3).
 #include <hip/hip_runtime.h>
 
@@ -49,6 +49,7 @@ struct sme_batch {
     int nitems = 0;
     int items_cap = 0;
     Slot *slots = nullptr;
+    unsigned *work = nullptr;  // the work counters of the three time slots
     ErrWord *err = nullptr;
     int cur = 0, sa = 0;
     int grid = 0;
@@ -145,6 +146,7 @@ BatchArgs make_args(const sme_batch *b)
     a.sa = b->sa;
     a.sb = (b->sa + 1) % 3;
     a.sc = (b->sa + 2) % 3;
+    a.work = b->work;
     a.err = b->err;
     a.g = b->p.g;
     a.c_slip = b->p.c_slip;
@@ -276,6 +278,7 @@ int sme_batch_init(sme_batch **out, int n, const int *levels, const sme_mesh *me
     alloc((void **)&b->b, boff * sizeof(double));
     alloc((void **)&b->inst, n * sizeof(BatchInst));
     alloc((void **)&b->slots, 3 * (size_t)n * sizeof(Slot));
+    alloc((void **)&b->work, 3 * kWorkStride * sizeof(unsigned));
     alloc((void **)&b->err, sizeof(ErrWord));
     alloc((void **)&b->quad_dev, 2 * kMaxQuad * sizeof(double));
     if (!rc) {
@@ -296,6 +299,7 @@ int sme_batch_init(sme_batch **out, int n, const int *levels, const sme_mesh *me
                 e = hipMemcpyAsync(b->b + b->boff[i], bath[i], (size_t)b->nx[i] * b->ny[i] * sizeof(double),
                                    hipMemcpyHostToDevice, b->stream);
         if (e == hipSuccess) e = hipMemsetAsync(b->slots, 0, 3 * (size_t)n * sizeof(Slot), b->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(b->work, 0, 3 * kWorkStride * sizeof(unsigned), b->stream);
         if (e == hipSuccess) e = launch_slots_reset(b->slots, b->err, 0, b->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
         if (e != hipSuccess) rc = bfail(b, SME_EHIP, "batch upload: %s", hipGetErrorString(e));
@@ -438,7 +442,7 @@ int sme_batch_autotune(sme_batch *b, const char *cache_path)
     }
     int r = build_items(b);
     if (r) return r;
-    static const int cand[] = {2, 3, 4, 6, 8, 12, 16, 24, 32};
+    static const int cand[] = {2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64};
     hipEvent_t e0, e1;
     BCHK(b, hipEventCreate(&e0));
     BCHK(b, hipEventCreate(&e1));
@@ -482,6 +486,8 @@ int sme_batch_autotune(sme_batch *b, const char *cache_path)
     b->cur = 0;
     b->sa = 0;
     BCHK(b, hipMemsetAsync(b->slots, 0, 3 * (size_t)b->n * sizeof(Slot), b->stream));
+    // every step finds its counter at zero: steps clear the counter of the step after next
+    BCHK(b, hipMemsetAsync(b->work, 0, 3 * kWorkStride * sizeof(unsigned), b->stream));
     BCHK(b, launch_slots_reset(b->slots, b->err, 0, b->stream));
     BCHK(b, hipStreamSynchronize(b->stream));
     drop_graphs(b);
@@ -506,6 +512,7 @@ void sme_batch_destroy(sme_batch *b)
     (void)hipFree(b->inst);
     (void)hipFree(b->items);
     (void)hipFree(b->slots);
+    (void)hipFree(b->work);
     (void)hipFree(b->err);
     if (b->own_stream) (void)hipStreamDestroy(b->stream);
     delete b;

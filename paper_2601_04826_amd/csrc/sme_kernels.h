@@ -100,6 +100,10 @@ struct BatchItem {
     int inst, sx, sy, pad;  // one wave's work: strip sx, band sy of grid inst
 };
 
+// The work counters of the three time slots lie this many words apart (one
+// 256-byte line each).
+constexpr int kWorkStride = 64;
+
 struct BatchArgs {
     const double *q;
     double *qn;
@@ -109,6 +113,7 @@ struct BatchArgs {
     int nitems;
     Slot *slots;       // [n_inst][3]
     int sa, sb, sc;
+    unsigned *work;    // [3 * kWorkStride]: next item of the step that reads slot s at work[s * kWorkStride]
     ErrWord *err;
     double g, c_slip, nu, cfl;
     int implicit;
