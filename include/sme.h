@@ -105,8 +105,9 @@ typedef struct {
  *   kind SME_MESH_2D_STRUCT nx * ny cells on [x0,x1] x [y0,y1];
  *                           bc = {west, east, south, north}; periodic must pair.
  *   kind SME_MESH_2D_TRI    n_vert vertices vert_xy[2*v + {0,1}], n_tri
- *                           triangles tri[3*t + {0,1,2}] (CCW); every edge
- *                           used by one triangle only is a reflective wall. */
+ *                           triangles tri[3*t + {0,1,2}] (CCW), at most 2^28
+ *                           of them; every edge used by one triangle only is
+ *                           a reflective wall. */
 typedef struct {
     int kind;
     int64_t nx, ny;

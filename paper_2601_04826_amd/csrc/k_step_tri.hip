@@ -25,30 +25,95 @@ __device__ __forceinline__ void frame_side(Side<N, true> &S, double h, double b,
     side_flux<N, true>(S, g);
 }
 
-// Raw state of one face's neighbour and the face's scaled normal n |e|.
+// Field access.  Up to level kTriBufLevel through buffer descriptors: each
+// field is a uniform base (the descriptor, in scalar registers) and a lane's
+// element a 32-bit byte offset, so a gather of all fields of one cell costs
+// one offset, not one 64-bit address per field (nor the registers of those
+// addresses: at level 3 the kernel fits three waves per SIMD instead of two).
+// Triangle meshes hold at most 2^28 cells (checked when the mesh is read), so
+// every offset fits in 32 bits.  Above that level the descriptors of the many
+// fields no longer fit the scalar registers, and plain 64-bit addresses are
+// used.  Measured per level at 1 M triangles: the buffer path is 2-7 % faster
+// at levels 0-3 (three waves per SIMD at level 3); at level 4 (two waves per
+// SIMD either way) 64-bit addresses with the next face's loads in flight are
+// fastest; at levels 5-8 64-bit addresses without them (two waves per SIMD at
+// levels 5-6 instead of one or two).
+constexpr int kTriBufLevel = 3;
+constexpr int kTriPrefetchLevel = 4;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc_of(const void *base, int64_t bytes)
+{
+    const unsigned nrec = bytes > 0xFFFFFFFFll ? 0xFFFFFFFFu : (unsigned)bytes;
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)nrec, 0x00020000);
+}
+
+// element e of the field at base (stride elements per field)
+template <bool BUF>
+__device__ __forceinline__ double ld(const double *base, int64_t stride, int64_t e)
+{
+    if constexpr (BUF)
+        return __builtin_bit_cast(double,
+                                  __builtin_amdgcn_raw_buffer_load_b64(rsrc_of(base, stride * 8), (unsigned)e * 8u, 0, 0));
+    else
+        return base[e];
+}
+
+template <bool BUF>
+__device__ __forceinline__ int ld_i32(const int32_t *base, int64_t stride, int64_t e)
+{
+    if constexpr (BUF)
+        return (int)__builtin_amdgcn_raw_buffer_load_b32(rsrc_of(base, stride * 4), (unsigned)e * 4u, 0, 0);
+    else
+        return base[e];
+}
+
+template <bool BUF>
+__device__ __forceinline__ void st(double v, double *base, int64_t stride, int64_t e)
+{
+    if constexpr (BUF)
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, v),
+                                              rsrc_of(base, stride * 8), (unsigned)e * 8u, 0, 0);
+    else
+        base[e] = v;
+}
+
+// Raw state of one cell.
 template <int N>
-struct Gather {
+struct Raw {
     double h, b, qx[N + 1], qy[N + 1];
+};
+
+template <int N, bool BUF>
+__device__ __forceinline__ void load_raw(const StepArgs &a, int64_t e, Raw<N> &r)
+{
+    constexpr int n = N + 1;
+    r.h = ld<BUF>(a.q, a.stride, e);
+    r.b = ld<BUF>(a.b, a.stride, e);
+#pragma unroll
+    for (int k = 0; k < n; ++k) {
+        r.qx[k] = ld<BUF>(a.q + (1 + k) * a.stride, a.stride, e);
+        r.qy[k] = ld<BUF>(a.q + (1 + n + k) * a.stride, a.stride, e);
+    }
+}
+
+// What face s of cell i needs from memory besides its neighbour's index j (a
+// wall if j < 0): the neighbour's raw state (the cell's own for a wall,
+// mirrored at use) and the face's scaled normal n |e|.
+template <int N>
+struct FaceIn {
+    int j;
+    Raw<N> c;
     double sx, sy;
 };
 
-// Loads for the face at geometry index gi whose neighbour is j (a wall if j < 0:
-// only the geometry is loaded, the mirror state is formed at use).
-template <int N>
-__device__ __forceinline__ void gather(const StepArgs &a, int j, int64_t gi, Gather<N> &G)
+template <int N, bool BUF>
+__device__ __forceinline__ void load_face(const StepArgs &a, int64_t i, int s, int j, FaceIn<N> &f)
 {
-    constexpr int n = N + 1;
-    G.sx = a.fsx[gi];
-    G.sy = a.fsy[gi];
-    if (j >= 0) {
-        G.h = a.q[j];
-        G.b = a.b[j];
-#pragma unroll
-        for (int k = 0; k < n; ++k) {
-            G.qx[k] = a.q[(1 + k) * a.stride + j];
-            G.qy[k] = a.q[(1 + n + k) * a.stride + j];
-        }
-    }
+    const int64_t so = s * a.stride;
+    f.j = j;
+    load_raw<N, BUF>(a, j < 0 ? i : j, f.c);
+    f.sx = ld<BUF>(a.fsx + so, a.stride, i);
+    f.sy = ld<BUF>(a.fsy + so, a.stride, i);
 }
 
 // IMP: the friction step is backward Euler (compile-time copy of the flag)
@@ -57,6 +122,8 @@ __global__ __launch_bounds__(kBlock) void k_step_tri(StepArgs a)
 {
     constexpr int n = N + 1;
     constexpr int nf = 2 * n + 1;
+    constexpr bool BUF = N <= kTriBufLevel;
+    constexpr bool PRE = N == kTriPrefetchLevel;
     const double dt = step_dt(a);
     if (blockIdx.x == 0 && threadIdx.x == 0) slot_update(a, dt);
     if (dt == 0.0) {
@@ -71,50 +138,44 @@ __global__ __launch_bounds__(kBlock) void k_step_tri(StepArgs a)
     const int64_t i = slot * kBlock + threadIdx.x;
     double r = 0.0;
     if (i < a.ncells) {
-        double h0, b0, qx0[n], qy0[n];
-        h0 = a.q[i];
-        b0 = a.b[i];
-        const double iv = a.ivol[i];
-#pragma unroll
-        for (int k = 0; k < n; ++k) {
-            qx0[k] = a.q[(1 + k) * a.stride + i];
-            qy0[k] = a.q[(1 + n + k) * a.stride + i];
-        }
+        Raw<N> c0;
+        load_raw<N, BUF>(a, i, c0);
+        const double iv = ld<BUF>(a.ivol, a.stride, i);
         double acc[nf];
 #pragma unroll
         for (int f = 0; f < nf; ++f) acc[f] = 0.0;
-        // One face at a time (rolled: the live set is one face's two sides),
-        // with the gather of the next face's neighbour issued before the
-        // current face is evaluated, so its latency overlaps the arithmetic.
+        // One face at a time (rolled: the live set is one face's two sides).
+        // With PRE the loads of the next face are issued before the current
+        // face is evaluated: their registers against their latency, which
+        // pays where the kernel runs two waves per SIMD either way.
+        FaceIn<N> nxt;
         int jn[3];
+        if constexpr (PRE) {
 #pragma unroll
-        for (int s = 0; s < 3; ++s) jn[s] = a.nbr[s * a.stride + i];
-        Gather<N> nxt;
-        gather<N>(a, jn[0], i, nxt);
+            for (int s = 0; s < 3; ++s) jn[s] = ld_i32<BUF>(a.nbr + s * a.stride, a.stride, i);
+            load_face<N, BUF>(a, i, 0, jn[0], nxt);
+        }
 #pragma unroll 1
         for (int s = 0; s < 3; ++s) {
-            const Gather<N> cur = nxt;
-            if (s < 2) gather<N>(a, s == 0 ? jn[1] : jn[2], i + (s + 1) * a.stride, nxt);
-            const int j = s == 0 ? jn[0] : (s == 1 ? jn[1] : jn[2]);
+            FaceIn<N> cur;
+            if constexpr (PRE) {
+                cur = nxt;
+                if (s < 2) load_face<N, BUF>(a, i, s + 1, s == 0 ? jn[1] : jn[2], nxt);
+            } else {
+                load_face<N, BUF>(a, i, s, ld_i32<BUF>(a.nbr + s * a.stride, a.stride, i), cur);
+            }
+            const int j = cur.j;
+            Raw<N> &c1 = cur.c;
             double nx, ny, w;
             face_geom(cur.sx, cur.sy, iv, nx, ny, w);
-            double h1, b1, qx1[n], qy1[n];
-            if (j >= 0) {
-                h1 = cur.h;
-                b1 = cur.b;
+            if (j < 0) {  // reflective wall: mirror the normal momenta
+                c1.h = c0.h;
+                c1.b = c0.b;
 #pragma unroll
                 for (int k = 0; k < n; ++k) {
-                    qx1[k] = cur.qx[k];
-                    qy1[k] = cur.qy[k];
-                }
-            } else {  // reflective wall: mirror the normal momenta
-                h1 = h0;
-                b1 = b0;
-#pragma unroll
-                for (int k = 0; k < n; ++k) {
-                    double qn = fma(qx0[k], nx, qy0[k] * ny);
-                    qx1[k] = fma(-2.0 * qn, nx, qx0[k]);
-                    qy1[k] = fma(-2.0 * qn, ny, qy0[k]);
+                    double qn = fma(c0.qx[k], nx, c0.qy[k] * ny);
+                    c1.qx[k] = fma(-2.0 * qn, nx, c0.qx[k]);
+                    c1.qy[k] = fma(-2.0 * qn, ny, c0.qy[k]);
                 }
             }
             // canonical orientation: from the lower to the higher cell index,
@@ -125,14 +186,14 @@ __global__ __launch_bounds__(kBlock) void k_step_tri(StepArgs a)
             double qxl[n], qyl[n], qxr[n], qyr[n];
 #pragma unroll
             for (int k = 0; k < n; ++k) {
-                qxl[k] = own_left ? qx0[k] : qx1[k];
-                qyl[k] = own_left ? qy0[k] : qy1[k];
-                qxr[k] = own_left ? qx1[k] : qx0[k];
-                qyr[k] = own_left ? qy1[k] : qy0[k];
+                qxl[k] = own_left ? c0.qx[k] : c1.qx[k];
+                qyl[k] = own_left ? c0.qy[k] : c1.qy[k];
+                qxr[k] = own_left ? c1.qx[k] : c0.qx[k];
+                qyr[k] = own_left ? c1.qy[k] : c0.qy[k];
             }
             Side<N, true> L, R;
-            frame_side<N>(L, own_left ? h0 : h1, own_left ? b0 : b1, qxl, qyl, sx, sy, a.g);
-            frame_side<N>(R, own_left ? h1 : h0, own_left ? b1 : b0, qxr, qyr, sx, sy, a.g);
+            frame_side<N>(L, own_left ? c0.h : c1.h, own_left ? c0.b : c1.b, qxl, qyl, sx, sy, a.g);
+            frame_side<N>(R, own_left ? c1.h : c0.h, own_left ? c1.b : c0.b, qxr, qyr, sx, sy, a.g);
             double Fh[nf], D[nf];
             face_flux<N, true>(L, R, a.g, a.quad, Fh, D);
             // this cell's share, rotated from the frame (a, t) with normal (sx, sy) back to (x, y)
@@ -146,26 +207,30 @@ __global__ __launch_bounds__(kBlock) void k_step_tri(StepArgs a)
                 acc[1 + n + k] = fma(w, fma(ca, sy, ct * sx), acc[1 + n + k]);
             }
         }
-        double h = fma(-dt, acc[0], h0);
+        double h = fma(-dt, acc[0], c0.h);
         double qx[n], qy[n];
 #pragma unroll
         for (int k = 0; k < n; ++k) {
-            qx[k] = fma(-dt, acc[1 + k], qx0[k]);
-            qy[k] = fma(-dt, acc[1 + n + k], qy0[k]);
+            qx[k] = fma(-dt, acc[1 + k], c0.qx[k]);
+            qy[k] = fma(-dt, acc[1 + n + k], c0.qy[k]);
         }
         const double ih = rcp(h);
         friction_step<N, true, IMP>(qx, qy, ih, dt, a.c_slip, a.nu);
-        a.qn[i] = h;
+        st<BUF>(h, a.qn, a.stride, i);
         bool bad = !(h > 0.0) || !isfinite(h);
 #pragma unroll
         for (int k = 0; k < n; ++k) {
-            a.qn[(1 + k) * a.stride + i] = qx[k];
-            a.qn[(1 + n + k) * a.stride + i] = qy[k];
+            st<BUF>(qx[k], a.qn + (1 + k) * a.stride, a.stride, i);
+            st<BUF>(qy[k], a.qn + (1 + n + k) * a.stride, a.stride, i);
             bad |= !isfinite(qx[k]) || !isfinite(qy[k]);
         }
         flag_bad(a, bad);
-        double fw[3], fnx[3], fny[3];  // reloaded (cached) rather than held across the face loop
-        tri_geom(a, i, fnx, fny, fw);
+        // the face geometry again (cached) rather than held across the face loop
+        double fw[3], fnx[3], fny[3];
+#pragma unroll
+        for (int s = 0; s < 3; ++s)
+            face_geom(ld<BUF>(a.fsx + s * a.stride, a.stride, i), ld<BUF>(a.fsy + s * a.stride, a.stride, i), iv,
+                      fnx[s], fny[s], fw[s]);
         double lm;
         r = cfl_ratio_tri<N>(a.g, h, ih, qx, qy, fnx, fny, fw, &lm);
         if (!(r >= 0.0)) r = 0.0;

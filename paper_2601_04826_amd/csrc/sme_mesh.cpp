@@ -51,7 +51,7 @@ int check_mesh(const sme_mesh *m, int level, int *nf, int64_t *nc)
         return SME_OK;
     case SME_MESH_2D_TRI:
         if (m->n_tri < 1 || m->n_vert < 3 || !m->vert_xy || !m->tri) return SME_EINVAL;
-        if (m->n_tri > ((int64_t)1 << 31) - 1) return SME_EINVAL;
+        if (m->n_tri > kTriMaxCells) return SME_EINVAL;
         *nc = m->n_tri;
         return SME_OK;
     default:

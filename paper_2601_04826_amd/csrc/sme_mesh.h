@@ -14,6 +14,10 @@
 namespace sme {
 namespace mesh {
 
+// Largest triangle mesh: the triangle kernel addresses a cell within a field
+// by a 32-bit byte offset, and 2^28 cells keep every field under 2 GiB.
+constexpr int64_t kTriMaxCells = (int64_t)1 << 28;
+
 // number of state fields of a level on a mesh kind
 int nfields_of(int level, int kind);
 

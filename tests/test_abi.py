@@ -63,6 +63,14 @@ def test_layout_and_validation(sme):
     vert = np.array([[0.0, 0.0], [1.0, 0.0], [0.0, 1.0]])
     t, _ = sme.make_mesh(dict(kind="tri", vert=vert, tri=np.array([[0, 1, 2]], dtype=np.int32)))
     assert sme.sme_layout(2, t) == (7, 1, 256)
+    # at most 2^28 triangles (the triangle kernel's 32-bit byte offsets within a
+    # field); only the count is read when the layout is asked for
+    t.n_tri = 1 << 28
+    assert sme.sme_layout(0, t) == (3, 1 << 28, 1 << 28)
+    t.n_tri = (1 << 28) + 1
+    with pytest.raises(sme.SmeError) as e:
+        sme.sme_layout(0, t)
+    assert e.value.code == sme.SME_EINVAL
 
 
 @pytest.mark.parametrize("mesh", [
