@@ -9,6 +9,7 @@
 
 #include <algorithm>
 #include <array>
+#include <chrono>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -442,6 +443,16 @@ int sme_batch_autotune(sme_batch *b, const char *cache_path)
     }
     int r = build_items(b);
     if (r) return r;
+    // The GPU's clocks ramp up over the first tens of milliseconds of load:
+    // time no candidate before about 0.2 s of steps (the lake at rest does not
+    // change under them).
+    {
+        const auto t0 = std::chrono::steady_clock::now();
+        do {
+            BCHK(b, one_step(b));
+            BCHK(b, hipStreamSynchronize(b->stream));
+        } while (std::chrono::steady_clock::now() - t0 < std::chrono::milliseconds(200));
+    }
     static const int cand[] = {2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64};
     hipEvent_t e0, e1;
     BCHK(b, hipEventCreate(&e0));
