@@ -157,9 +157,37 @@ def warm_clocks(torch, chunk, seconds):
             return el
 
 
-def source_hash():
+# Library sources each workload's launches are built from, besides every
+# header and k_misc.hip (slots, reductions), which all of them include or run.
+# A change to any other source leaves its committed counter figures valid.
+_STEP = ("sme_lib.cpp",)
+WORKLOAD_SOURCES = {
+    "struct_2d_1024_l2": ("k_step_2d.hip",) + _STEP,
+    "struct_2d_4096_l2": ("k_step_2d.hip",) + _STEP,
+    "struct_2d_2048_l8": ("k_step_2d.hip",) + _STEP,
+    "struct_2d_1024_l2_implicit": ("k_step_2d.hip",) + _STEP,
+    "tri_4m_l3": ("k_step_tri.hip", "sme_mesh.cpp") + _STEP,
+    "dam_break_1d": ("k_step_1d.hip",) + _STEP,
+    "batch_512": ("k_batch.hip", "sme_batch.cpp"),
+    "closure_2048": ("k_closure.hip", "k_mlp.hip", "sme_closure.cpp", "k_step_2d.hip", "k_step_1d.hip") + _STEP,
+    "vam_1d": ("k_vam.hip", "sme_vam.cpp"),
+    "struct_2d_1024_l2_o2": ("k_step2.hip",) + _STEP,
+    "lift_1024_l2": ("k_lift.hip", "k_step_2d.hip") + _STEP,
+}
+
+
+def source_hash(workload=None):
+    """Hash of the library sources a workload runs (every source for None or
+    an unknown workload)."""
+    csrc = os.path.join(ROOT, "paper_2601_04826_amd", "csrc")
+    files = sorted(glob.glob(os.path.join(csrc, "*")))
+    own = WORKLOAD_SOURCES.get(workload)
+    if own is not None:
+        files = [f for f in files
+                 if f.endswith(".h") or os.path.basename(f) in own or os.path.basename(f) == "k_misc.hip"]
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2601_04826_amd", "csrc", "*"))):
+    for f in files:
+        h.update(os.path.basename(f).encode())
         with open(f, "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -173,7 +201,7 @@ def load_traffic(workload, launches_bytes):
         return None
     with open(path) as f:
         d = json.load(f)
-    if d.get("source_hash") != source_hash():
+    if d.get("source_hash") != source_hash(workload):
         return None
     return d.get("bytes_per_launch")
 
@@ -187,7 +215,7 @@ def load_flops(workload):
         return None
     with open(path) as f:
         d = json.load(f)
-    if d.get("source_hash") != source_hash():
+    if d.get("source_hash") != source_hash(workload):
         return None
     return d.get("fp64_flops_per_launch")
 

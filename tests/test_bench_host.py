@@ -35,6 +35,28 @@ def test_counter_figures_follow_the_source_hash(tmp_path, monkeypatch):
     assert bench.load_flops("w") is None
 
 
+def test_workload_hash_covers_its_own_sources_and_every_header(tmp_path, monkeypatch):
+    csrc = tmp_path / "paper_2601_04826_amd" / "csrc"
+    csrc.mkdir(parents=True)
+    for f in ("k_step_2d.hip", "k_vam.hip", "k_misc.hip", "sme_lib.cpp", "common.h"):
+        (csrc / f).write_text(f"// {f} v1\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    wl = "struct_2d_1024_l2"
+    h = bench.source_hash(wl)
+    (csrc / "k_vam.hip").write_text("// another kernel, changed\n")
+    assert bench.source_hash(wl) == h
+    assert bench.source_hash() != h  # the whole-library hash sees it
+    for f in ("k_step_2d.hip", "sme_lib.cpp", "k_misc.hip", "common.h"):
+        (csrc / f).write_text("// changed\n")
+        assert bench.source_hash(wl) != h, f
+        h = bench.source_hash(wl)
+    assert set(bench.WORKLOAD_SOURCES) == set(bench.WORKLOADS)
+    real = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2601_04826_amd", "csrc")
+    for files in bench.WORKLOAD_SOURCES.values():
+        for f in files:
+            assert os.path.exists(os.path.join(real, f)), f
+
+
 def test_committed_workloads_are_known():
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     for f in os.listdir(os.path.join(root, "profiles")):
