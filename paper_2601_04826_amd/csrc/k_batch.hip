@@ -5,11 +5,11 @@
 // (costliest first).  Each resident wave takes the next item from a device
 // counter when it is done with the previous one, so the waves finish together
 // even when the items are few and tall (a fixed deal of a few tall items per
-// wave leaves some waves one item behind the rest).  Each grid keeps its own three time
-// slots, so every grid takes its own CFL step; the item holding the grid's
-// first band also advances that grid's clock.  The band code is the one of the
-// single-grid kernel, so a grid advanced here is bitwise identical to the same
-// grid advanced alone.
+// wave leaves some waves one item behind the rest).  Each grid keeps its own
+// three time slots, so every grid takes its own CFL step; the item holding the
+// grid's first band also advances that grid's clock.  The band code is the one
+// of the single-grid kernel, so a grid advanced here is bitwise identical to
+// the same grid advanced alone.
 #include <hip/hip_runtime.h>
 
 #include "sme_band2d.h"
@@ -35,8 +35,8 @@ __global__ __launch_bounds__(kBlock) void k_batch_step(BatchArgs B)
     if (blockIdx.x == 0 && threadIdx.x == 0) (void)atomicExch(B.work + B.sc * kWorkStride, 0u);
     unsigned got = 0;
     if (lane == 0) got = atomicAdd(ctr, 1u);
-    int it = (int)__builtin_amdgcn_readfirstlane(got);
-    while (it < B.nitems) {
+    unsigned it = (unsigned)__builtin_amdgcn_readfirstlane(got);
+    while (it < (unsigned)B.nitems) {
         // the index of the wave's next item is fetched while this one runs
         got = 0;
         if (lane == 0) got = atomicAdd(ctr, 1u);
@@ -89,7 +89,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_step(BatchArgs B)
         r = wave_max(r);
         if (lane == 0 && r > 0.0)
             atomicMax(&a.slots[a.sb].r[blockIdx.x % kRatioWords].bits, (unsigned long long)__double_as_longlong(r));
-        it = (int)__builtin_amdgcn_readfirstlane(got);
+        it = (unsigned)__builtin_amdgcn_readfirstlane(got);
     }
 }
 
