@@ -1,8 +1,10 @@
-"""Host logic of bench.py (CPU): algorithmic bytes per cell, and the committed
+"""Host logic of bench.py (CPU): algorithmic bytes per cell, the committed
 counter figures (HBM traffic, executed FP64 flops) that are reported only while
-the kernel sources still hash to the value they were taken on."""
+the sources of their workload still hash to the value they were taken on, and
+the clock warm-up before the timed steps."""
 import json
 import os
+import time
 
 import bench
 
@@ -55,6 +57,29 @@ def test_workload_hash_covers_its_own_sources_and_every_header(tmp_path, monkeyp
     for files in bench.WORKLOAD_SOURCES.values():
         for f in files:
             assert os.path.exists(os.path.join(real, f)), f
+
+
+def test_clock_warmup_runs_until_its_time_is_spent():
+    calls = []
+
+    class FakeCuda:
+        @staticmethod
+        def synchronize():
+            calls.append("sync")
+
+    class FakeTorch:
+        cuda = FakeCuda
+
+    def chunk():
+        calls.append("chunk")
+        time.sleep(0.01)
+
+    el = bench.warm_clocks(FakeTorch, chunk, 0.05)
+    assert el >= 0.05
+    n = calls.count("chunk")
+    assert 5 <= n <= 20 and calls.count("sync") == n
+    calls.clear()
+    assert bench.warm_clocks(FakeTorch, chunk, 0.0) >= 0.0 and calls.count("chunk") == 1  # always one chunk
 
 
 def test_committed_workloads_are_known():
