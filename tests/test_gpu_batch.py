@@ -119,6 +119,54 @@ def test_batch_tiny_grids_bitwise_equal_single_grid(sme):
     bt.close()
 
 
+def single_runs(sme, probs, steps):
+    out = []
+    for p in probs:
+        s = sme.Solver(p)
+        s.set_state(p["q"])
+        t, n = s.run(steps)
+        out.append((s.get_state(), t, n))
+        s.close()
+    return out
+
+
+def test_batch_work_counter_edge_cases(sme):
+    """The device counter the waves take their items from: an ensemble of one
+    one-cell grid (a single item for the whole persistent grid of waves), and
+    an ensemble whose band heights change between runs (1 row: many items;
+    1024 rows: one band per strip), each run a mix of graph replays and single
+    launches; every grid stays bitwise equal to the same grid advanced alone,
+    with the same clock."""
+    one = [tiny_grid(1, 1, 2, "wall", 500)]
+    print("one-cell ensemble", flush=True)
+    bt = sme.Batch(one)
+    bt.set_state(0, one[0]["q"])
+    bt.run(13)
+    (q1, t1, n1), = single_runs(sme, one, 13)
+    assert n1 == 13 and np.array_equal(bt.get_state(0), q1) and bt.time(0)[0] == t1
+    bt.close()
+    probs = [tiny_grid(nx, ny, lv, bc, 510 + k)
+             for k, (nx, ny, lv, bc) in enumerate([(70, 45, 1, "periodic"), (9, 130, 4, "wall"),
+                                                   (200, 3, 2, "extrap"), (33, 33, 3, "wall")])]
+    print("ensemble with changing band heights:", [(p["nx"], p["ny"], p["level"]) for p in probs], flush=True)
+    bt = sme.Batch(probs)
+    for i, p in enumerate(probs):
+        bt.set_state(i, p["q"])
+    bt.run(7)
+    for lv in range(5):
+        bt.set_rows(lv, 1)
+    bt.run(12)
+    for lv in range(5):
+        bt.set_rows(lv, 1024)
+    bt.run(11)
+    ref = single_runs(sme, probs, 30)
+    for i, (q1, t1, n1) in enumerate(ref):
+        assert n1 == 30
+        assert np.array_equal(bt.get_state(i), q1), i
+        assert bt.time(i)[0] == t1
+    bt.close()
+
+
 def test_batch_autotune_and_cache(sme, tmp_path):
     probs = small_batch(n=8, seed=90)
     bt = sme.Batch(probs)
