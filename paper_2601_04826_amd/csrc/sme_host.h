@@ -61,27 +61,53 @@ inline int device_cus()
 }
 
 // Height of the row band each wave of the structured kernel marches up.
-// Every band costs its rows plus about 1.5 rows of halo work, and waves run in
-// generations of (compute units x 4 SIMDs x waves per SIMD); a short last
-// generation costs a full band time.  Pick the height that minimises
-// generations x (rows + 1.5) for this grid, level and device.
-inline int pick_rows(int level, int64_t nx, int64_t ny, int cus)
+// Every band costs its rows plus about 1.5 rows of halo work; N waves (strips
+// x bands) run on S resident wave slots (compute units x 4 SIMDs x waves per
+// SIMD).
+// - In step: the waves of a generation start and end together, and a short
+//   last generation costs a whole band time: cost ceil(N / S) x (rows + 1.5).
+//   This holds at one wave per SIMD, and where the best such choice needs at
+//   most two generations.
+// - Otherwise (more generations at two or more waves per SIMD) the waves
+//   drift apart, and the step costs about N / S band times plus one band at
+//   the end: (N / S + 1) x (rows + 1.5).
+// (Measured with warm clocks, same box, against the first rule everywhere:
+// 2-5 % faster at 4096^2 levels 1, 2 and 4 and at 6144^2 level 2, 9 % at
+// 8192^2 level 0; 3072^2 level 2 and every smaller grid measured keep the
+// first rule's choice.)
+inline int rows_by_cost(bool drift, int64_t slots, int64_t nsx, int64_t ny, int64_t *gens_out)
 {
-    const int per_simd = step_2d_waves_per_simd(level);
-    const int64_t slots = (int64_t)cus * 4 * per_simd;
-    const int64_t nsx = (nx + 61) / 62;
     int best = 8;
     double best_cost = 1e300;
+    int64_t best_gens = 1;
     for (int rows = 2; rows <= 64; ++rows) {
         const int64_t waves = nsx * ((ny + rows - 1) / rows);
-        const int64_t gens = (waves + slots - 1) / slots;
-        const double cost = (double)gens * (rows + 1.5);
+        const int64_t g = (waves + slots - 1) / slots;
+        const double gens = drift ? (double)waves / (double)slots + 1.0 : (double)g;
+        const double cost = gens * (rows + 1.5);
         if (cost < best_cost - 1e-9) {
             best_cost = cost;
             best = rows;
+            best_gens = g;
         }
     }
+    if (gens_out) *gens_out = best_gens;
     return best;
+}
+
+inline int pick_rows_for(int per_simd, int64_t nx, int64_t ny, int cus)
+{
+    const int64_t slots = (int64_t)cus * 4 * per_simd;
+    const int64_t nsx = (nx + 61) / 62;
+    int64_t gens = 1;
+    const int in_step = rows_by_cost(false, slots, nsx, ny, &gens);
+    if (per_simd < 2 || gens <= 2) return in_step;
+    return rows_by_cost(true, slots, nsx, ny, nullptr);
+}
+
+inline int pick_rows(int level, int64_t nx, int64_t ny, int cus)
+{
+    return pick_rows_for(step_2d_waves_per_simd(level), nx, ny, cus);
 }
 
 }  // namespace host
