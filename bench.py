@@ -286,7 +286,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU decomposition "
-              "is a design, not part of this build", file=sys.stderr)
+              "is designed but not implemented", file=sys.stderr)
         sys.exit(2)
 
     import torch
